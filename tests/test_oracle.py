@@ -1,0 +1,338 @@
+"""Pins of the FP64 oracle against brute force, invariants and the paper's numbers.
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term, a
+transposed operand, a wrong row/column index, summation in the wrong order,
+a missing zero-initialisation) fails at least one of them.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import spgen
+from _golden import kv
+
+
+def rand_coo(rng, m, n, nnz, dup=True, ints=True):
+    r = rng.integers(0, m, nnz).astype(np.int32) if m else np.zeros(0, np.int32)
+    c = rng.integers(0, n, nnz).astype(np.int32) if n else np.zeros(0, np.int32)
+    if not dup:
+        key = np.unique(r.astype(np.int64) * max(n, 1) + c)
+        r, c = (key // max(n, 1)).astype(np.int32), (key % max(n, 1)).astype(np.int32)
+        p = rng.permutation(r.size)
+        r, c = r[p], c[p]
+    v = rng.integers(-8, 9, r.size).astype(np.float64) if ints else rng.uniform(-1, 1, r.size)
+    return r, c, v
+
+
+def dense_from_coo(m, n, r, c, v):
+    D = np.zeros((m, n), dtype=np.float64)
+    for a, b, x in zip(r, c, v):
+        D[a, b] += x
+    return D
+
+
+def dense(A):
+    D = np.zeros((A.m, A.n), dtype=np.float64)
+    D[A.row_of(), A.colind] = A.values
+    return D
+
+
+SHAPES = [(1, 1), (5, 7), (7, 5), (16, 16), (33, 17), (64, 64), (3, 0), (0, 4)]
+
+
+# ---------------------------------------------------------------- CSR assembly
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_csr_from_coo_brute_force(m, n):
+    rng = np.random.default_rng(m * 100 + n)
+    nnz = 0 if m == 0 or n == 0 else 3 * (m + n)
+    r, c, v = rand_coo(rng, m, n, nnz)
+    A = oracle.csr_from_coo(m, n, r, c, v)
+    # canonical structure (Sec. 3): rptrs[0]=0, rptrs[m]=tau, cids sorted per row
+    assert A.rowptr[0] == 0 and A.rowptr[-1] == A.nnz == A.colind.size
+    assert (np.diff(A.rowptr) >= 0).all()
+    for i in range(m):
+        cols = A.colind[A.rowptr[i]:A.rowptr[i + 1]]
+        assert (np.diff(cols) > 0).all()
+    # the stored set of (i, j) is exactly the set of input positions, and
+    # values equal the dense accumulation (integers: exact in any order)
+    D = dense_from_coo(m, n, r, c, v)
+    assert (dense(A) == D).all()
+    assert A.nnz == np.unique(r.astype(np.int64) * max(n, 1) + c).size
+
+
+def test_csr_from_coo_scipy_third_opinion():
+    rng = np.random.default_rng(11)
+    r, c, v = rand_coo(rng, 50, 40, 600)
+    A = oracle.csr_from_coo(50, 40, r, c, v)
+    S = sp.coo_matrix((v, (r, c)), shape=(50, 40)).tocsr()
+    S.sum_duplicates()
+    S.sort_indices()
+    assert (S.indptr == A.rowptr).all() and (S.indices == A.colind).all()
+    assert (S.data == A.values).all()
+
+
+def test_duplicates_summed_in_input_order():
+    # (1e16 + 1) rounds to 1e16, so input order gives 0; any reordering that
+    # adds the cancelling pair first gives 1.
+    r = np.array([0, 0, 0], np.int32)
+    c = np.array([2, 2, 2], np.int32)
+    v = np.array([1e16, 1.0, -1e16])
+    A = oracle.csr_from_coo(1, 3, r, c, v)
+    assert A.nnz == 1 and A.values[0] == 0.0
+    A2 = oracle.csr_from_coo(1, 3, r, c, v[[0, 2, 1]])
+    assert A2.values[0] == 1.0
+
+
+def test_round_trip_identity():
+    coo = spgen.powerlaw(3_000, 2_500, 2.0, 400, 12.0, seed=5)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    sh = spgen.shuffled(spgen.COO(A.m, A.n, A.row_of(), A.colind, A.values), seed=9)
+    B = oracle.csr_from_coo(sh.m, sh.n, sh.r, sh.c, sh.v)
+    assert (A.rowptr == B.rowptr).all() and (A.colind == B.colind).all()
+    assert (A.values.view(np.uint64) == B.values.view(np.uint64)).all()
+
+
+def test_out_of_range_rejected():
+    with pytest.raises(ValueError):
+        oracle.csr_from_coo(2, 2, np.array([0, 2]), np.array([0, 0]), np.array([1.0, 1.0]))
+    with pytest.raises(ValueError):
+        oracle.csr_from_coo(2, 2, np.array([0, 1]), np.array([0, -1]), np.array([1.0, 1.0]))
+
+
+# ---------------------------------------------------------------- binning
+
+@pytest.mark.parametrize("upper", [[4, 64, 1024], [0, 1, 2, 8, 32], [1_000_000]])
+def test_bin_rows_partition(upper):
+    coo = spgen.powerlaw(4_000, 4_000, 2.0, 2_000, 16.0, seed=2)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    perm, off = oracle.bin_rows(A.rowptr, upper)
+    L = A.row_lengths()
+    assert off[0] == 0 and off[-1] == A.m and (np.diff(off) >= 0).all()
+    assert np.array_equal(np.sort(perm), np.arange(A.m))
+    # brute force: bin index = number of thresholds strictly below L, capped
+    nb = len(upper)
+    b = np.minimum(np.searchsorted(np.asarray(upper), L, side="left"), nb - 1)
+    expect = np.argsort(b, kind="stable")
+    assert np.array_equal(perm, expect)
+    for k in range(nb):
+        rows = perm[off[k]:off[k + 1]]
+        assert (np.diff(rows) > 0).all()
+        Lk = L[rows]
+        if k < nb - 1:
+            assert (Lk <= upper[k]).all()
+        if k > 0:
+            assert (Lk > upper[k - 1]).all()
+
+
+# ---------------------------------------------------------------- SpMV
+
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_spmv_dense_brute_force_exact(m, n):
+    rng = np.random.default_rng(m * 7 + n)
+    nnz = 0 if m == 0 or n == 0 else 4 * (m + n)
+    r, c, v = rand_coo(rng, m, n, nnz)
+    A = oracle.csr_from_coo(m, n, r, c, v)
+    x = rng.integers(-8, 9, n).astype(np.float64)
+    y = oracle.spmv(A, x)
+    # integer inputs: every partial sum is exact, so any order agrees exactly
+    Di = dense_from_coo(m, n, r, c, v).astype(np.int64)
+    assert (y == (Di @ x.astype(np.int64)).astype(np.float64)).all()
+
+
+def test_spmv_float_matches_dense_and_scipy():
+    rng = np.random.default_rng(1)
+    r, c, v = rand_coo(rng, 64, 48, 900, ints=False)
+    A = oracle.csr_from_coo(64, 48, r, c, v)
+    x = rng.uniform(-1, 1, 48)
+    y = oracle.spmv(A, x)
+    yd = dense(A) @ x
+    ys = sp.csr_matrix((A.values, A.colind, A.rowptr), shape=(64, 48)) @ x
+    assert oracle.rel2(y, yd) < 1e-14 and oracle.rel2(y, ys) < 1e-14
+    # sequential ascending-p order, checked by an explicit loop
+    for i in (0, 17, 63):
+        s = 0.0
+        for p in range(A.rowptr[i], A.rowptr[i + 1]):
+            s = s + A.values[p] * x[A.colind[p]]
+        assert y[i] == s
+
+
+def test_spmv_identity_and_permutation():
+    n = 1000
+    x = spgen.uniform(n, 0)
+    I = oracle.csr_from_coo(n, n, np.arange(n), np.arange(n), np.ones(n))
+    assert (oracle.spmv(I, x) == x).all()
+    perm = np.random.default_rng(4).permutation(n)
+    P = oracle.csr_from_coo(n, n, np.arange(n), perm, np.ones(n))
+    assert (oracle.spmv(P, x) == x[perm]).all()
+
+
+def test_spmv_unit_vectors_give_columns():
+    coo = spgen.powerlaw(300, 200, 2.0, 100, 8.0, seed=3)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    D = dense(A)
+    for j in (0, 5, 199):
+        e = np.zeros(A.n)
+        e[j] = 1.0
+        assert (oracle.spmv(A, e) == D[:, j]).all()
+
+
+def test_spmv_ones_gives_row_sums_and_empty_rows_positive_zero():
+    coo = spgen.powerlaw(2000, 2000, 2.0, 300, 4.0, seed=8)
+    # drop every third row to create empty rows
+    keep = coo.r % 3 != 0
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r[keep], coo.c[keep], coo.v[keep])
+    y = oracle.spmv(A, np.ones(A.n))
+    for i in range(A.m):
+        s = 0.0
+        for p in range(A.rowptr[i], A.rowptr[i + 1]):
+            s = s + A.values[p]
+        assert y[i] == s
+    empty = A.row_lengths() == 0
+    assert empty.sum() > 0 and (y[empty] == 0).all() and not np.signbit(y[empty]).any()
+
+
+def test_spmv_linearity():
+    coo = spgen.workload_c0()
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    x, z = spgen.uniform(A.n, 1), spgen.uniform(A.n, 2)
+    a, b = 0.75, -1.5
+    lhs = oracle.spmv(A, a * x + b * z)
+    rhs = a * oracle.spmv(A, x) + b * oracle.spmv(A, z)
+    scale = oracle.spmv_abs(A, np.abs(a * x) + np.abs(b * z))
+    assert (np.abs(lhs - rhs) <= 1e-14 * scale + 1e-300).all()
+
+
+def test_spmv_laplacian27_exact():
+    N = 9
+    coo = spgen.stencil3d(N, N, N, 27, values="laplacian")
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    y = oracle.spmv(A, np.ones(A.n))
+    L = A.row_lengths()
+    # row sum = 26 - (L - 1): zero on interior rows
+    assert (y == 26.0 - (L - 1)).all() and (y[L == 27] == 0).all()
+
+
+def test_spmv_thread_count_invariant():
+    coo = spgen.powerlaw(20_000, 20_000, 2.0, 2_000, 16.0, seed=1)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    x = spgen.uniform(A.n, 3)
+    y1 = oracle.spmv(A, x, nthreads=1)
+    y4 = oracle.spmv(A, x, nthreads=4)
+    assert (y1.view(np.uint64) == y4.view(np.uint64)).all()
+
+
+# ---------------------------------------------------------------- SpMM
+
+@pytest.mark.parametrize("k", [1, 3, 16])
+def test_spmm_columns_are_spmv(k):
+    coo = spgen.powerlaw(1500, 1200, 2.0, 300, 10.0, seed=4)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    X = spgen.uniform(A.n * k, 5).reshape(A.n, k)
+    Y = oracle.spmm(A, X)
+    for j in range(k):
+        assert (Y[:, j].view(np.uint64) == oracle.spmv(A, X[:, j].copy()).view(np.uint64)).all()
+
+
+def test_spmm_dense_brute_force_exact():
+    rng = np.random.default_rng(21)
+    m, n, k = 40, 30, 5
+    r, c, v = rand_coo(rng, m, n, 300)
+    A = oracle.csr_from_coo(m, n, r, c, v)
+    X = rng.integers(-8, 9, (n, k)).astype(np.float64)
+    Y = oracle.spmm(A, X)
+    Di = dense_from_coo(m, n, r, c, v).astype(np.int64)
+    assert (Y == (Di @ X.astype(np.int64))).all()
+
+
+# ---------------------------------------------------------------- transpose / sampled dot
+
+def test_spmv_t_dense_exact_and_untouched_columns():
+    rng = np.random.default_rng(31)
+    m, n = 50, 70
+    r, c, v = rand_coo(rng, m, n, 200)
+    c = np.where(c >= 60, c - 10, c).astype(np.int32)  # columns 60..69 untouched
+    A = oracle.csr_from_coo(m, n, r, c, v)
+    dy = rng.integers(-8, 9, m).astype(np.float64)
+    dx = oracle.spmv_t(A, dy)
+    Di = dense_from_coo(m, n, r, c, v).astype(np.int64)
+    assert (dx == (Di.T @ dy.astype(np.int64))).all()
+    assert (dx[60:] == 0).all() and not np.signbit(dx[60:]).any()
+    dY = rng.integers(-8, 9, (m, 3)).astype(np.float64)
+    assert (oracle.spmv_t(A, dY) == Di.T @ dY.astype(np.int64)).all()
+
+
+def test_adjoint_identity():
+    coo = spgen.powerlaw(5_000, 4_000, 2.0, 500, 20.0, seed=6)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    x, dy = spgen.uniform(A.n, 1), spgen.normal(A.m, 2)
+    lhs = float(np.dot(oracle.spmv_t(A, dy), x))
+    rhs = float(np.dot(dy, oracle.spmv(A, x)))
+    scale = float(np.dot(np.abs(dy), oracle.spmv_abs(A, np.abs(x))))
+    assert abs(lhs - rhs) <= 1e-13 * scale
+
+
+def test_sddmm_closed_form():
+    coo = spgen.powerlaw(800, 900, 2.0, 200, 10.0, seed=7)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    x, dy = spgen.uniform(A.n, 1), spgen.normal(A.m, 2)
+    dv = oracle.sddmm(A, dy, x)
+    assert (dv == dy[A.row_of()] * x[A.colind]).all()
+    X, dY = spgen.uniform(A.n * 4, 3).reshape(-1, 4), spgen.normal(A.m * 4, 4).reshape(-1, 4)
+    dv4 = oracle.sddmm(A, dY, X)
+    rows = A.row_of()
+    for p in (0, 17, A.nnz - 1):
+        s = 0.0
+        for t in range(4):
+            s = s + dY[rows[p], t] * X[A.colind[p], t]
+        assert dv4[p] == s
+
+
+# ---------------------------------------------------------------- counting formulas and UCLD
+
+def test_byte_and_flop_model_matches_paper():
+    g = kv("worked_examples.txt")
+    assert int(g["bytes_per_nonzero"]) == 8 + 4
+    assert abs(2 / 12 - float(g["flop_per_byte"])) < 1e-15
+    assert float(g["sustained_gbs"]) * 2 / 12 == float(g["spmv_cap_gflops"])
+    for n, tau in [(1, 1), (10_000, 100_000), (1 << 20, 16_777_216)]:
+        expect = int(g["app_bytes_const"]) + int(g["app_bytes_per_row"]) * n + \
+            int(g["app_bytes_per_nonzero"]) * tau
+        assert oracle.app_bytes(n, n, tau) == expect
+    # Sec. 5: 8 m k + 8 n k + (n + 1) 4 + tau (8 + 4)
+    m = n = 1 << 20
+    tau, k = 16_777_216, 16
+    assert oracle.app_bytes(m, n, tau, k) == 8 * m * k + 8 * n * k + (n + 1) * 4 + tau * 12
+    assert oracle.flops(tau, k) == 2 * tau * k
+
+
+def test_ucld_worked_example():
+    g = kv("worked_examples.txt")
+    cols = [int(t) for t in g["ucld_row_columns"].split()]
+    line = int(g["ucld_line_doubles"])
+    A = oracle.csr_from_coo(1, 64, np.zeros(len(cols)), cols, np.ones(len(cols)))
+    assert oracle.ucld(A, line) == float(g["ucld_value"])
+    worst = oracle.csr_from_coo(1, 64, np.zeros(4), [0, 8, 16, 24], np.ones(4))
+    best = oracle.csr_from_coo(1, 64, np.zeros(8), list(range(8, 16)), np.ones(8))
+    assert oracle.ucld(worst, line) == float(g["ucld_worst"])
+    assert oracle.ucld(best, line) == float(g["ucld_best"])
+
+
+def test_dense_block_bytes_example():
+    g = kv("worked_examples.txt")
+    # 64 nonzeros of one dense 8 x 8 region: CRS stores value + column id each
+    assert 64 * (8 + 4) == int(g["dense_block_crs_bytes"])
+    assert 64 * 8 + 4 == int(g["dense_block_blocked_bytes"])
+
+
+def test_compensated_sum_pin_values():
+    # 1.0 followed by 4096 copies of 2^-25: plain FP32 accumulation stays at 1.0
+    # (each addend is below half an ulp of 1), the exact sum is 1 + 2^-13.
+    terms = np.array([1.0] + [2.0 ** -25] * 4096)
+    s32 = np.float32(0)
+    for t in terms.astype(np.float32):
+        s32 = np.float32(s32 + t)
+    assert s32 == np.float32(1.0)
+    A = oracle.csr_from_coo(1, terms.size, np.zeros(terms.size), np.arange(terms.size), terms)
+    assert oracle.spmv(A, np.ones(terms.size))[0] == 1.0001220703125 == 1 + 2.0 ** -13
