@@ -1,0 +1,219 @@
+/*
+ * spx.h -- C ABI of the MI355X (gfx950) CSR sparse-matrix library.
+ *
+ * Problem statement (paper Sec. 1 and Sec. 3): for an m x n sparse matrix A
+ * stored in compressed row storage -- rptrs (here `rowptr`, m+1 entries,
+ * rowptr[0] = 0, rowptr[m] = tau), cids (here `colind`, tau column ids) and
+ * val (here `values`, tau entries) -- compute y <- A x (SpMV) and, for a dense
+ * n x k matrix X, Y <- A X (SpMM, Sec. 5).  Indices are 32-bit (Sec. 4).
+ *
+ * Conventions for every entry point below:
+ *  - Pointers are DEVICE pointers unless the parameter name starts with
+ *    `host_`.  The caller owns every buffer (including workspaces sized by the
+ *    matching *_workspace_bytes call); the library never allocates or frees
+ *    device memory on the compute path and never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are asynchronous and stream ordered, except where a comment says the call
+ *    synchronises.
+ *  - Errors are returned as spx_status; spx_last_error() returns a text for
+ *    the last non-OK status of the calling thread.  Argument checks (sizes,
+ *    null pointers, dtype pairs, workspace size) happen before any launch; a
+ *    call that returns an error has launched nothing.
+ *  - Structural validity of the CSR arrays (monotone rowptr, rowptr[m] = nnz,
+ *    0 <= colind < n) is NOT re-checked by the compute calls; use
+ *    csr_validate first for untrusted input.  Columns need not be sorted
+ *    within a row for SpMV/SpMM; csr_from_coo produces sorted columns.
+ *  - Outputs are overwritten (beta = 0).  An empty row gives +0.0.  m == 0 is a
+ *    no-op returning SPX_OK.
+ *  - Floating point: FP64 values use FP64 arithmetic throughout.  FP32/BF16
+ *    values with FP32 x/y accumulate in FP32; rows longer than the plan's
+ *    kahan_len use compensated accumulation and an FP64 cross-lane reduction.
+ *    Results are deterministic: the same inputs and plan give the same bits.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPX_OK = 0,
+  SPX_ERR_INVALID = 1,     /* bad size, null pointer, bad option */
+  SPX_ERR_UNSUPPORTED = 2, /* dtype pair or layout not implemented */
+  SPX_ERR_WORKSPACE = 3,   /* workspace missing or too small */
+  SPX_ERR_HIP = 4          /* a HIP runtime call or launch failed */
+} spx_status;
+
+typedef enum {
+  SPX_F64 = 0,
+  SPX_F32 = 1,
+  SPX_BF16 = 2 /* raw IEEE bfloat16 bits in uint16 */
+} spx_dtype;
+
+#define SPX_MAX_BINS 12
+
+/* Row-binning plan options (rows grouped by length; the GPU analogue of the
+ * paper's dynamic row chunks, Sec. 4.1).  Bin b holds the rows whose length
+ * L satisfies upper[b-1] < L <= upper[b]; the last bin takes all longer
+ * rows (its upper[] entry is ignored).  lanes[b] is the number of threads that
+ * cooperate on one row of bin b: 1, 2, 4, 8, 16, 32, 64 (one wavefront) or
+ * 256 (one workgroup); 0 marks a split bin (allowed only as the last bin):
+ * each row is cut into segments of split_chunk nonzeros, one workgroup per
+ * segment, and the segment partial sums are reduced in segment order. */
+#define SPX_FLAG_NO_NT_STORE 1u  /* plain (temporal) stores for y / Y */
+#define SPX_FLAG_SCALAR_X 2u     /* SpMM: one element per lane, no vector loads of X */
+#define SPX_FLAG_NO_XCD_MAP 4u   /* keep hardware workgroup order (no per-XCD contiguous tiles) */
+typedef struct spx_plan_opts {
+  int32_t nbins;
+  int32_t upper[SPX_MAX_BINS];
+  int32_t lanes[SPX_MAX_BINS];
+  int32_t split_chunk; /* >= 256; nonzeros per segment of a split row */
+  int32_t kahan_len;   /* FP32 accumulation: rows with L > kahan_len are compensated */
+  int32_t max_k;       /* widest SpMM right-hand side the plan serves (>= 1) */
+  uint32_t flags;      /* SPX_FLAG_* */
+  int32_t reserved[4];
+} spx_plan_opts;
+
+typedef struct spx_plan spx_plan;   /* opaque host object */
+typedef struct spx_batch spx_batch; /* opaque host object */
+
+/* Text for the last non-OK status returned on this thread ("" if none). */
+const char *spx_last_error(void);
+
+/* Library version string and the device it was compiled for ("gfx950"). */
+const char *spx_version(void);
+
+/* Default plan options for SpMV (k = 1) or SpMM with k right-hand sides and
+ * values of type vtype.  Never fails for k >= 1. */
+spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan_opts *opts);
+
+/* ---------------------------------------------------------------- assembly
+ * COO triplets -> canonical CSR (Sec. 3): rows ascending, columns strictly
+ * ascending within a row.  Duplicate (i, j) triplets are merged by summing
+ * their values in input order (FP64, one add at a time).  r, c: int32[nnz_in];
+ * v: f64[nnz_in].  Outputs rowptr int32[m+1], colind int32[nnz_in] and values
+ * f64[nnz_in] (capacity nnz_in); *nnz_out (device int32) receives the stored
+ * count, or -1 if some triplet is out of range (then the other outputs are
+ * unspecified).  Requires nnz_in < 2^31.  Workspace: csr_from_coo_workspace_bytes. */
+spx_status csr_from_coo_workspace_bytes(int32_t m, int32_t n, int64_t nnz_in, size_t *bytes);
+spx_status csr_from_coo(int32_t m, int32_t n, int64_t nnz_in, const int32_t *r, const int32_t *c,
+                        const double *v, int32_t *rowptr, int32_t *colind, double *values,
+                        int32_t *nnz_out, void *workspace, size_t ws_bytes, void *stream);
+
+/* Structural check of CSR arrays on the device.  *status_out (device int32)
+ * receives 0 if rowptr[0] = 0, rowptr is non-decreasing, rowptr[m] = nnz and
+ * 0 <= colind[p] < n for every p; otherwise the code of the most severe
+ * problem found: 4 rowptr[0] != 0 or rowptr[m] != nnz, 3 a row whose range is
+ * decreasing or outside [0, nnz], 2 a column out of range, 1 an unsorted or
+ * repeated column inside a row (checked only when check_sorted != 0). */
+spx_status csr_validate(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr,
+                        const int32_t *colind, int32_t check_sorted, int32_t *status_out,
+                        void *stream);
+
+/* ---------------------------------------------------------------- plans
+ * A plan bins the rows of one sparsity pattern by length (row_perm lists bin
+ * 0's rows, then bin 1's, ..., ascending inside each bin) and, for a split
+ * bin, cuts its rows into segments.  The plan's device arrays live in the
+ * caller's workspace, which must stay allocated and unmodified while the plan
+ * is used.  csr_plan_create reads the device rowptr and SYNCHRONISES `stream`
+ * (it copies the bin sizes back to the host).  The plan may be used with any
+ * values/x/X of the same pattern; SpMM with the plan needs k <= opts.max_k. */
+spx_status csr_plan_workspace_bytes(int32_t m, int32_t nnz, const spx_plan_opts *opts, size_t *bytes);
+spx_status csr_plan_create(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr,
+                           const spx_plan_opts *opts, void *workspace, size_t ws_bytes,
+                           void *stream, spx_plan **out);
+/* Copies row_perm (int32[m]) and bin_off (int32[nbins+1]) to host memory;
+ * synchronous. */
+spx_status csr_plan_export_bins(const spx_plan *plan, int32_t *host_row_perm, int32_t *host_bin_off);
+/* Number of split segments and split rows of the plan. */
+spx_status csr_plan_info(const spx_plan *plan, int32_t *nbins, int32_t *nsplit_rows, int32_t *nsegments);
+void csr_plan_destroy(spx_plan *plan);
+
+/* ---------------------------------------------------------------- products
+ * y <- A x.  vtype/xytype pairs: (F64, F64) plain FP64; (F32, F32) and
+ * (BF16, F32) reduced-precision values with FP32 vectors.  x has n entries,
+ * y has m.  plan == NULL uses a single unbinned kernel (lanes per row chosen
+ * from nnz/m) and needs no workspace. */
+spx_status csr_spmv(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                    const void *values, spx_dtype vtype, const void *x, void *y, spx_dtype xytype,
+                    const spx_plan *plan, void *stream);
+
+/* Y <- A X (Sec. 5).  X is n x k row-major with leading dimension ldx >= k,
+ * Y is m x k row-major with ldy >= k (element strides).  Same dtype pairs as
+ * csr_spmv.  For each row a zeroed accumulator of k entries collects
+ * val[p] * X[colind[p], :]. */
+spx_status csr_spmm(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                    const void *values, spx_dtype vtype, int32_t k, const void *X, int64_t ldx,
+                    void *Y, int64_t ldy, spx_dtype xytype, const spx_plan *plan, void *stream);
+
+/* ---------------------------------------------------------------- transpose / gradients
+ * CSC index of a CSR pattern (the CCS dual, Sec. 3), built on the device:
+ * colptr int32[n+1]; rowind int32[nnz] and perm int32[nnz] list, column by
+ * column and in ascending row order inside a column, the row and the CSR
+ * position of each nonzero.  Deterministic. */
+spx_status csr_transpose_index_workspace_bytes(int32_t m, int32_t n, int32_t nnz, size_t *bytes);
+spx_status csr_transpose_index(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr,
+                               const int32_t *colind, int32_t *colptr, int32_t *rowind,
+                               int32_t *perm, void *workspace, size_t ws_bytes, void *stream);
+
+/* dX <- A^T dY.  dY is m x k (lddy), dX is n x k (lddx), row-major.
+ * mode 0 (CSC index, deterministic): needs colptr/rowind/perm from
+ * csr_transpose_index; every column is a gather in ascending row order, run
+ * by the product kernels over the CSC pattern (values read through perm).
+ * `plan` (nullable) must then be a plan of the CSC pattern: created from
+ * colptr with n rows.  mode 1 (atomic scatter): colptr/rowind/perm may be
+ * NULL; dX is zeroed and then accumulated with atomic adds (summation order
+ * not deterministic); `plan` (nullable) is then a plan of the CSR pattern and
+ * only sets the traversal. */
+spx_status csr_spmv_t(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                      const int32_t *colptr, const int32_t *rowind, const int32_t *perm,
+                      const void *values, spx_dtype vtype, int32_t k, const void *dY, int64_t lddy,
+                      void *dX, int64_t lddx, spx_dtype xytype, int32_t mode, const spx_plan *plan,
+                      void *stream);
+
+/* Sampled dot: out[p] = sum_t dY[row(p), t] * X[colind[p], t] for every
+ * stored nonzero p (the gradient of y = A(values) x with respect to values).
+ * dtype F64 or F32 for dY, X and out alike.  `plan` (nullable) is a plan of
+ * the CSR pattern and only sets the traversal (rows by bins). */
+spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                     int32_t k, const void *dY, int64_t lddy, const void *X, int64_t ldx, void *out,
+                     spx_dtype dtype, const spx_plan *plan, void *stream);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent products Y_b <- A_b X_b in ONE persistent kernel launch.
+ * Each descriptor names one CSR matrix, its right-hand side and its plan
+ * options (from an autotuner or spx_plan_default_opts).  csr_batch_create
+ * bins every matrix on the device, builds the work-tile list in the caller's
+ * workspace and SYNCHRONISES `stream`.  csr_batch_run is a single launch of a
+ * counter-reset kernel plus the persistent kernel, capturable into a HIP
+ * graph (it uses no memset).  Each matrix's result is bit-identical to
+ * csr_spmm (k > 1) or csr_spmv (k = 1) with a plan created from the same
+ * options. */
+typedef struct spx_csr_desc {
+  int32_t m, n, nnz, k;
+  const int32_t *rowptr;
+  const int32_t *colind;
+  const void *values;
+  const void *X; /* x when k = 1 */
+  void *Y;       /* y when k = 1 */
+  int64_t ldx, ldy;
+  spx_dtype vtype, xytype;
+  spx_plan_opts opts;
+} spx_csr_desc;
+
+spx_status csr_batch_workspace_bytes(int32_t count, const spx_csr_desc *host_descs, size_t *bytes);
+spx_status csr_batch_create(int32_t count, const spx_csr_desc *host_descs, void *workspace,
+                            size_t ws_bytes, void *stream, spx_batch **out);
+spx_status csr_batch_run(const spx_batch *batch, void *stream);
+/* Tiles, workgroups of the persistent launch, and total split segments. */
+spx_status csr_batch_info(const spx_batch *batch, int64_t *ntiles, int32_t *grid, int64_t *nsegments);
+void csr_batch_destroy(spx_batch *batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPX_H */

@@ -1,0 +1,123 @@
+"""Per-matrix autotuner for plan options (bin thresholds, lanes per row,
+split chunk).
+
+Candidates are timed on the GPU with HIP events (median of `reps` launches of
+csr_spmv / csr_spmm on the current stream); the fastest wins.  Decisions are
+cached in a JSON file keyed by a hash of the sparsity structure, k and the
+value dtype; an unreadable or mismatched cache entry is ignored (the matrix
+is tuned again, or the default heuristic is used when tuning is off).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import torch
+
+from ._lib import PlanOpts
+from .ops import CSR, Plan, default_opts, spmm, spmv
+
+
+def structure_key(A: CSR, k: int) -> str:
+    h = hashlib.sha1()
+    h.update(f"{A.m}x{A.n}:{A.nnz}:k{k}:{A.values.dtype}".encode())
+    h.update(A.rowptr.cpu().numpy().tobytes())
+    if A.nnz:
+        step = max(1, A.nnz // 65536)
+        h.update(A.colind[::step].cpu().numpy().tobytes())
+    return h.hexdigest()
+
+
+def _copy(o: PlanOpts) -> PlanOpts:
+    return PlanOpts.from_dict(o.to_dict())
+
+
+def candidates(k: int, vdtype=torch.float64) -> list:
+    """A small family around the defaults: lane widths halved / doubled,
+    split chunk halved / doubled, split disabled, and a coarse 3-bin plan."""
+    base = default_opts(k, vdtype)
+    out = [base]
+    half = _copy(base)
+    dbl = _copy(base)
+    for b in range(base.nbins):
+        l = base.lanes[b]
+        if l:
+            half.lanes[b] = max(1, l // 2) if l != 256 else 64
+            dbl.lanes[b] = min(64, l * 2) if l < 64 else 256
+    out += [half, dbl]
+    if base.lanes[base.nbins - 1] == 0:
+        for f in (0.5, 2.0):
+            c = _copy(base)
+            c.split_chunk = max(256, int(base.split_chunk * f))
+            out.append(c)
+        nosplit = _copy(base)
+        nosplit.lanes[base.nbins - 1] = 256
+        out.append(nosplit)
+    coarse = PlanOpts.from_dict({"nbins": 3, "upper": [8, 256], "lanes": [1 if k > 1 else 4, 64, 0],
+                                 "split_chunk": base.split_chunk, "kahan_len": base.kahan_len,
+                                 "max_k": k, "flags": 0})
+    out.append(coarse)
+    return out
+
+
+def load_cache(path: str | None) -> dict:
+    if not path or not os.path.exists(path):
+        return {}
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _valid(entry) -> PlanOpts | None:
+    try:
+        o = PlanOpts.from_dict(entry["opts"])
+        if not (1 <= o.nbins <= 12) or len(entry["opts"]["lanes"]) != o.nbins:
+            return None
+        return o
+    except (KeyError, TypeError, ValueError):
+        return None
+
+
+def time_opts(A: CSR, X: torch.Tensor, opts: PlanOpts, reps: int = 5) -> float:
+    plan = Plan.for_matrix(A, opts)
+    vec = X.dim() == 1
+    out = torch.empty((A.m,) if vec else (A.m, X.shape[1]), dtype=X.dtype, device=X.device)
+    call = (lambda: spmv(A, X, y=out, plan=plan)) if vec else (lambda: spmm(A, X, Y=out, plan=plan))
+    call()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        ts.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ts)
+    return ms[len(ms) // 2]
+
+
+def tune(A: CSR, X: torch.Tensor, reps: int = 5, cache_path: str | None = None,
+         cands: list | None = None) -> tuple:
+    """Return (best PlanOpts, report dict).  X is x (1-D) or X (n x k)."""
+    k = 1 if X.dim() == 1 else X.shape[1]
+    key = structure_key(A, k)
+    cache = load_cache(cache_path)
+    if key in cache:
+        o = _valid(cache[key])
+        if o is not None:
+            return o, {"cached": True, "ms": cache[key].get("ms")}
+    cands = cands if cands is not None else candidates(k, A.values.dtype)
+    times = [time_opts(A, X, o, reps) for o in cands]
+    best = min(range(len(cands)), key=lambda i: times[i])
+    report = {"cached": False, "ms": times[best], "all_ms": times, "choice": best}
+    if cache_path:
+        cache[key] = {"opts": cands[best].to_dict(), "ms": times[best]}
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f)
+        os.replace(tmp, cache_path)
+    return cands[best], report

@@ -1,0 +1,110 @@
+// product.hip -- fused, row-binned CSR products on gfx950:
+//   y <- A x  (SpMV, paper Sec. 3)        and        Y <- A X  (SpMM, Sec. 5)
+// plus the same traversal for the transpose gather (CSC index) and the
+// sampled dot (gradient with respect to the values).
+//
+// One launch covers every bin of a plan.  Workgroups [bins[i].blk_begin,
+// bins[i+1].blk_begin) serve bin i; long-row bins come first so that their
+// workgroups start early.  Inside a bin, a row is served by a group of
+// S slots x KL lanes: the KL lanes cover the k columns of one X row (VEC
+// elements each, one 16-byte load per lane when VEC > 1), the S slots walk
+// the row's nonzeros with stride S.  SpMV is the case KL = VEC = 1.
+//   - colind / values are streamed with non-temporal loads, x / X rows are
+//     gathered through L2, y / Y rows are written with non-temporal stores
+//     (the analogue of the paper's no-read, non-globally-ordered stores).
+//   - Each lane keeps U = 4 independent nonzeros in flight per iteration: the
+//     x gather is latency bound (paper Sec. 4.2), so memory-level parallelism
+//     is what buys throughput.
+//   - Partial sums of the S slots are combined with DPP / swizzle exchanges
+//     (and LDS across the 4 waves of a workgroup-per-row bin).
+//   - A split bin cuts each long row into segments of `chunk` nonzeros, one
+//     workgroup per segment.  Segment partials go to workspace; the last
+//     workgroup to arrive (agent-scope counter) sums them in segment order and
+//     resets the counter, so results are deterministic and no second launch or
+//     memset is needed.
+// FP32/BF16 values with FP32 vectors accumulate in FP32; rows longer than
+// kahan_len use error-free transforms (TwoProduct + TwoSum) per lane and an
+// FP64 cross-lane / cross-segment reduction, rounded to FP32 once at the end.
+#include "product_impl.hpp"
+
+namespace spx {
+
+namespace {
+
+using namespace prod;
+
+template <class C>
+__global__ __launch_bounds__(kWG) void k_product(const ProdArgs a) {
+  const int b = blockIdx.x;
+  int bi = 0;
+  while (bi + 1 < a.nbins && b >= a.bins[bi + 1].blk_begin) ++bi;
+  const BinDesc d = a.bins[bi];
+  const int lb = b - d.blk_begin;
+  const int tile = (a.flags & SPX_FLAG_NO_XCD_MAP) ? lb : xcd_tile(lb, d.nblk);
+  switch (d.lanes + (d.rpg > 1 ? 1000 : 0)) {
+    case 1: do_rows<C, 1, 1>(a, d, tile); break;
+    case 2: do_rows<C, 2, 1>(a, d, tile); break;
+    case 4: do_rows<C, 4, 1>(a, d, tile); break;
+    case 8: do_rows<C, 8, 1>(a, d, tile); break;
+    case 16: do_rows<C, 16, 1>(a, d, tile); break;
+    case 32: do_rows<C, 32, 1>(a, d, tile); break;
+    case 64: do_rows<C, 64, 1>(a, d, tile); break;
+    case 256: do_rows<C, 256, 1>(a, d, tile); break;
+    case 1001:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 1, 4>(a, d, tile);
+      else do_rows<C, 1, 1>(a, d, tile);
+      break;
+    case 1002:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 2, 4>(a, d, tile);
+      else do_rows<C, 2, 1>(a, d, tile);
+      break;
+    case 1004:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 4, 4>(a, d, tile);
+      else do_rows<C, 4, 1>(a, d, tile);
+      break;
+    case 1008:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 8, 4>(a, d, tile);
+      else do_rows<C, 8, 1>(a, d, tile);
+      break;
+    case 1016:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 16, 4>(a, d, tile);
+      else do_rows<C, 16, 1>(a, d, tile);
+      break;
+    case 1032:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 32, 4>(a, d, tile);
+      else do_rows<C, 32, 1>(a, d, tile);
+      break;
+    default: do_split<C>(a, d, tile); break;
+  }
+}
+
+template <typename VT, typename XT, int VECMAX>
+spx_status launch_vt(ProdArgs& a, int kl, int vec, unsigned grid, hipStream_t st) {
+#define SPX_CASE(KL_, VEC_)                                                         \
+  if (kl == KL_ && vec == VEC_) {                                                   \
+    k_product<Cfg<VT, XT, KL_, VEC_>><<<grid, kWG, 0, st>>>(a);                     \
+    SPX_LAUNCHED("k_product");                                                      \
+    return SPX_OK;                                                                  \
+  }
+  SPX_CASE(1, 1) SPX_CASE(2, 1) SPX_CASE(4, 1) SPX_CASE(8, 1) SPX_CASE(16, 1) SPX_CASE(32, 1)
+  SPX_CASE(1, VECMAX) SPX_CASE(2, VECMAX) SPX_CASE(4, VECMAX) SPX_CASE(8, VECMAX)
+  SPX_CASE(16, VECMAX) SPX_CASE(32, VECMAX)
+#undef SPX_CASE
+  return fail(SPX_ERR_UNSUPPORTED, "no product kernel for KL=%d VEC=%d", kl, vec);
+}
+
+}  // namespace
+
+spx_status launch_product(ProdArgs& a, int vt, int xt, int kl, int vec, hipStream_t st) {
+  int64_t grid = 0;
+  for (int i = 0; i < a.nbins; ++i) grid = a.bins[i].blk_begin + a.bins[i].nblk;
+  if (grid == 0) return SPX_OK;
+  if (grid > 0x7fffffff) return fail(SPX_ERR_UNSUPPORTED, "grid too large");
+  const unsigned g = static_cast<unsigned>(grid);
+  if (vt == SPX_F64 && xt == SPX_F64) return launch_vt<double, double, 2>(a, kl, vec, g, st);
+  if (vt == SPX_F32 && xt == SPX_F32) return launch_vt<float, float, 4>(a, kl, vec, g, st);
+  if (vt == SPX_BF16 && xt == SPX_F32) return launch_vt<uint16_t, float, 4>(a, kl, vec, g, st);
+  return fail(SPX_ERR_UNSUPPORTED, "unsupported value/vector dtype pair (%d, %d)", vt, xt);
+}
+
+}  // namespace spx

@@ -1,0 +1,420 @@
+// product_impl.hpp -- device side of the row-group products, shared by the
+// single-matrix launch (product.hip) and the persistent batched launch
+// (batch.hip).  See product.hip for the design.
+#pragma once
+
+#include <type_traits>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spx {
+namespace prod {
+
+constexpr int kUnroll = 4;
+
+template <typename VT_, typename XT_, int KL_, int VEC_>
+struct Cfg {
+  using VT = VT_;  // stored value type: double, float or uint16_t (bf16 bits)
+  using XT = XT_;  // vector / dense type: double or float
+  using AT = XT_;  // accumulation type of the plain path
+  static constexpr int KL = KL_;
+  static constexpr int VEC = VEC_;
+  static constexpr bool kComp = std::is_same<XT_, float>::value;
+};
+
+template <typename T, int N>
+struct VecT {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
+
+template <typename T, int N>
+__device__ __forceinline__ void load_x(const T* p, T (&out)[N]) {
+  if constexpr (N == 1) {
+    out[0] = *p;
+  } else {
+    typedef typename VecT<T, N>::type V;
+    V v = *reinterpret_cast<const V*>(p);
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = v[i];
+  }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_y(T* p, const T (&in)[N], bool nt) {
+  if constexpr (N == 1) {
+    if (nt) __builtin_nontemporal_store(in[0], p); else *p = in[0];
+  } else {
+    typedef typename VecT<T, N>::type V;
+    V v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = in[i];
+    if (nt) __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+    else *reinterpret_cast<V*>(p) = v;
+  }
+}
+
+template <class C>
+__device__ __forceinline__ typename C::XT value_at(const ProdArgs& a, int32_t p) {
+  const int32_t q = a.vperm ? ld_stream(a.vperm + p) : p;
+  return static_cast<typename C::XT>(
+      ValueLoad<typename C::VT>::get(static_cast<const typename C::VT*>(a.values) + q));
+}
+
+// Accumulate the nonzeros p = p0 + slot, p0 + slot + S, ... < p1 of one row
+// into acc (plain) or cacc (compensated) for the VEC columns at `col`.
+template <class C, int S>
+__device__ __forceinline__ void accumulate(const ProdArgs& a, int32_t p0, int32_t p1, int slot,
+                                           int col, bool comp, typename C::AT (&acc)[C::VEC],
+                                           Comp (&cacc)[C::VEC]) {
+  using XT = typename C::XT;
+  constexpr int VEC = C::VEC;
+  const XT* X = static_cast<const XT*>(a.X) + col;
+  const int64_t ldx = a.ldx;
+  int32_t p = p0 + slot;
+  if (!C::kComp || !comp) {
+    for (; p + (kUnroll - 1) * S < p1; p += kUnroll * S) {
+      int32_t c[kUnroll];
+      XT v[kUnroll];
+      XT xv[kUnroll][VEC];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        c[u] = ld_stream(a.colind + p + u * S);
+        v[u] = value_at<C>(a, p + u * S);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) load_x<XT, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = fma_t(v[u], xv[u][e], acc[e]);
+    }
+    for (; p < p1; p += S) {
+      const int32_t c = ld_stream(a.colind + p);
+      const XT v = value_at<C>(a, p);
+      XT xv[VEC];
+      load_x<XT, VEC>(X + static_cast<int64_t>(c) * ldx, xv);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = fma_t(v, xv[e], acc[e]);
+    }
+  } else if constexpr (C::kComp) {
+    for (; p + (kUnroll - 1) * S < p1; p += kUnroll * S) {
+      int32_t c[kUnroll];
+      float v[kUnroll];
+      float xv[kUnroll][VEC];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        c[u] = ld_stream(a.colind + p + u * S);
+        v[u] = value_at<C>(a, p + u * S);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) load_x<float, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) cacc[e].add_prod(v[u], xv[u][e]);
+    }
+    for (; p < p1; p += S) {
+      const int32_t c = ld_stream(a.colind + p);
+      const float v = value_at<C>(a, p);
+      float xv[VEC];
+      load_x<float, VEC>(X + static_cast<int64_t>(c) * ldx, xv);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) cacc[e].add_prod(v, xv[e]);
+    }
+  }
+}
+
+// Begin/end of the rows served by a row group: binned rows read their id from
+// row_perm and their nonzero range from prange (both precomputed by the plan,
+// one independent load each); unbinned rows read rowptr.
+__device__ __forceinline__ void row_range(const ProdArgs& a, const BinDesc& d, int idx, int32_t& row,
+                                          int32_t& p0, int32_t& p1) {
+  if (a.row_perm) {
+    row = a.row_perm[d.row_begin + idx];
+    const int2 pr = reinterpret_cast<const int2*>(a.prange)[d.row_begin + idx];
+    p0 = pr.x;
+    p1 = pr.y;
+  } else {
+    row = d.row_begin + idx;
+    p0 = a.rowptr[row];
+    p1 = a.rowptr[row + 1];
+  }
+}
+
+// Sum over the S slots of a row group and store the row's VEC outputs.
+template <class C, int GG>
+__device__ __forceinline__ void finish_small(const ProdArgs& a, bool active, bool comp, int slot,
+                                             int col, int32_t row, typename C::AT (&acc)[C::VEC],
+                                             Comp (&cacc)[C::VEC], bool nt) {
+  constexpr int KL = C::KL, VEC = C::VEC;
+  using XT = typename C::XT;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) acc[e] = group_sum<GG, KL>(acc[e]);
+  double dsum[VEC] = {};
+  if constexpr (C::kComp) {
+    if (__any(comp)) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) dsum[e] = group_sum<GG, KL>(comp ? cacc[e].value() : 0.0);
+    }
+  }
+  if (active && slot == 0 && col < a.k) {
+    XT out[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      if constexpr (C::kComp) out[e] = comp ? static_cast<XT>(dsum[e]) : acc[e];
+      else out[e] = acc[e];
+    }
+    store_y<XT, VEC>(static_cast<XT*>(a.Y) + static_cast<int64_t>(row) * a.ldy + col, out, nt);
+  }
+}
+
+// Row groups of G threads (G in 1..64 or 256), R rows per group.
+//  R == 1: the group walks its row with U independent nonzeros per lane.
+//  R > 1 (short-row bins, at most one nonzero per slot and row): the group
+//  serves R rows at once and issues all their loads before using any, so a
+//  lane has R independent load chains in flight.  Rows of round j are the
+//  consecutive bin entries tile*RPB + j*NG + group, which keeps the row_perm,
+//  prange and y accesses of a round contiguous.
+template <class C, int G, int R>
+__device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int tile) {
+  constexpr int KL = C::KL, VEC = C::VEC;
+  constexpr int S = (G >= KL) ? G / KL : 1;
+  constexpr int GG = S * KL;
+  constexpr int NG = kWG / GG;  // groups per workgroup
+  constexpr int RPB = NG * R;   // rows per workgroup
+  using XT = typename C::XT;
+  using AT = typename C::AT;
+  if (tile * RPB >= d.nrows) return;  // whole workgroup idle (uniform)
+  const int t = threadIdx.x;
+  const int ln = t % GG, slot = ln / KL, kl = ln % KL, grp = t / GG;
+  const bool nt = !(a.flags & SPX_FLAG_NO_NT_STORE);
+
+  if constexpr (R > 1) {
+    static_assert(GG <= kWave, "multi-row groups live inside one wavefront");
+    int32_t row[R], p0[R], p1[R];
+    bool active[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int idx = tile * RPB + j * NG + grp;
+      active[j] = idx < d.nrows;
+      row[j] = 0;
+      p0[j] = 0;
+      p1[j] = 0;
+      if (active[j]) row_range(a, d, idx, row[j], p0[j], p1[j]);
+    }
+    for (int c0 = 0; c0 < a.k; c0 += KL * VEC) {
+      const int col = c0 + kl * VEC;
+      const XT* X = static_cast<const XT*>(a.X) + col;
+      int32_t c[R];
+      XT v[R];
+      bool has[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int32_t p = p0[j] + slot;
+        has[j] = (p < p1[j]) && (col < a.k);
+        c[j] = has[j] ? ld_stream(a.colind + p) : 0;
+        v[j] = has[j] ? value_at<C>(a, p) : XT(0);
+      }
+      XT xv[R][VEC];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (has[j]) {
+          load_x<XT, VEC>(X + static_cast<int64_t>(c[j]) * a.ldx, xv[j]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) xv[j][e] = XT(0);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const bool comp = C::kComp && (p1[j] - p0[j] > a.kahan_len);
+        AT acc[VEC];
+        Comp cacc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          cacc[e].init();
+          if (C::kComp && comp) {
+            cacc[e].add_prod(v[j], xv[j][e]);
+            acc[e] = AT(0);
+          } else {
+            acc[e] = fma_t(v[j], xv[j][e], AT(0));
+          }
+        }
+        // the planner only gives R > 1 to bins whose rows fit one nonzero
+        // per slot; any longer row is still summed, one nonzero at a time
+        if (col < a.k) {
+          for (int32_t p = p0[j] + S + slot; p < p1[j]; p += S) {
+            const XT vv = value_at<C>(a, p);
+            XT xx[VEC];
+            load_x<XT, VEC>(X + static_cast<int64_t>(ld_stream(a.colind + p)) * a.ldx, xx);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+              if (C::kComp && comp) cacc[e].add_prod(vv, xx[e]);
+              else acc[e] = fma_t(vv, xx[e], acc[e]);
+            }
+          }
+        }
+        finish_small<C, GG>(a, active[j], comp, slot, col, row[j], acc, cacc, nt);
+      }
+    }
+    return;
+  } else {
+    const int idx = tile * NG + grp;
+    const bool active = idx < d.nrows;
+    int32_t row = 0, p0 = 0, p1 = 0;
+    if (active) row_range(a, d, idx, row, p0, p1);
+    const bool comp = C::kComp && (p1 - p0 > a.kahan_len);
+    XT* Y = static_cast<XT*>(a.Y);
+
+    for (int c0 = 0; c0 < a.k; c0 += KL * VEC) {
+      const int col = c0 + kl * VEC;
+      AT acc[VEC];
+      Comp cacc[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        acc[e] = AT(0);
+        cacc[e].init();
+      }
+      if (col < a.k) accumulate<C, S>(a, p0, p1, slot, col, comp, acc, cacc);
+
+      if constexpr (GG <= kWave) {
+        finish_small<C, GG>(a, active, comp, slot, col, row, acc, cacc, nt);
+      } else {
+        // one row per workgroup: waves reduce, then LDS across the 4 waves
+        __shared__ double red[kWG / kWave][KL][VEC];
+        const int w = t / kWave;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          double v;
+          if constexpr (C::kComp) {
+            v = comp ? group_sum<kWave, KL>(cacc[e].value())
+                     : static_cast<double>(group_sum<kWave, KL>(acc[e]));
+          } else {
+            v = group_sum<kWave, KL>(acc[e]);
+          }
+          if ((t % kWave) < KL) red[w][t % kWave][e] = v;
+        }
+        __syncthreads();
+        if (t < KL && col < a.k) {
+          XT out[VEC];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            if (C::kComp && comp) {
+              double s = 0.0;
+              for (int i = 0; i < kWG / kWave; ++i) s += red[i][t][e];
+              out[e] = static_cast<XT>(s);
+            } else {
+              AT s = AT(0);
+              for (int i = 0; i < kWG / kWave; ++i) s += static_cast<AT>(red[i][t][e]);
+              out[e] = s;
+            }
+          }
+          store_y<XT, VEC>(Y + static_cast<int64_t>(row) * a.ldy + col, out, nt);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// One workgroup per segment of a split row; the last arrival reduces.
+template <class C>
+__device__ __forceinline__ void do_split(const ProdArgs& a, const BinDesc& d, int tile) {
+  constexpr int KL = C::KL, VEC = C::VEC;
+  constexpr int S = kWG / KL;
+  using XT = typename C::XT;
+  using AT = typename C::AT;
+  if (tile >= d.nrows) return;
+  __shared__ double red[kWG / kWave][KL][VEC];
+  __shared__ int last;
+  const int t = threadIdx.x, w = t / kWave, slot = t / KL, kl = t % KL;
+  const int32_t s = a.seg_row[tile];
+  const int32_t row = a.split_rows[s];
+  const int32_t f = a.seg_first[s], nseg = a.seg_first[s + 1] - f;
+  const int32_t rb = a.rowptr[row], re = a.rowptr[row + 1];
+  const int32_t p0 = rb + (tile - f) * a.chunk;
+  const int32_t p1 = min(p0 + a.chunk, re);
+  const bool comp = C::kComp && (re - rb > a.kahan_len);
+  double* part = a.partials + static_cast<int64_t>(tile) * a.max_k;
+
+  for (int c0 = 0; c0 < a.k; c0 += KL * VEC) {
+    const int col = c0 + kl * VEC;
+    AT acc[VEC];
+    Comp cacc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      acc[e] = AT(0);
+      cacc[e].init();
+    }
+    if (col < a.k) accumulate<C, S>(a, p0, p1, slot, col, comp, acc, cacc);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      double v;
+      if constexpr (C::kComp) {
+        v = comp ? group_sum<kWave, KL>(cacc[e].value())
+                 : static_cast<double>(group_sum<kWave, KL>(acc[e]));
+      } else {
+        v = group_sum<kWave, KL>(acc[e]);
+      }
+      if ((t % kWave) < KL) red[w][t % kWave][e] = v;
+    }
+    __syncthreads();
+    if (t < KL && col < a.k) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        double r;
+        if (C::kComp && comp) {
+          r = 0.0;
+          for (int i = 0; i < kWG / kWave; ++i) r += red[i][t][e];
+        } else {
+          AT q = AT(0);
+          for (int i = 0; i < kWG / kWave; ++i) q += static_cast<AT>(red[i][t][e]);
+          r = static_cast<double>(q);
+        }
+        __hip_atomic_store(part + col + e, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- arrival.  The partials were written by the lanes t < KL of wave 0
+  // with device-scope stores (written through to the device coherence
+  // point); vmcnt(0) waits until they have completed, so they are visible to
+  // device-scope loads of any XCD before the counter moves.  The last arrival
+  // reads them with device-scope loads.  This avoids a release/acquire fence
+  // pair, which on gfx950 writes back / invalidates the whole L2 of the XCD.
+  if (t == 0) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    const int old = __hip_atomic_fetch_add(a.counters + s, 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    last = (old == nseg - 1);
+  }
+  __syncthreads();
+  if (!__builtin_amdgcn_readfirstlane(last)) return;
+  const bool nt = !(a.flags & SPX_FLAG_NO_NT_STORE);
+  XT* Y = static_cast<XT*>(a.Y);
+  for (int c = t; c < a.k; c += kWG) {
+    const double* pp = a.partials + static_cast<int64_t>(f) * a.max_k + c;
+    XT out[1];
+    if (C::kComp && comp) {
+      double r = 0.0;
+      for (int j = 0; j < nseg; ++j)
+        r += __hip_atomic_load(pp + static_cast<int64_t>(j) * a.max_k, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      out[0] = static_cast<XT>(r);
+    } else {
+      AT r = AT(0);
+      for (int j = 0; j < nseg; ++j)
+        r += static_cast<AT>(__hip_atomic_load(pp + static_cast<int64_t>(j) * a.max_k,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      out[0] = r;
+    }
+    store_y<XT, 1>(Y + static_cast<int64_t>(row) * a.ldy + c, out, nt);
+  }
+  if (t == 0)
+    __hip_atomic_store(a.counters + s, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace prod
+}  // namespace spx

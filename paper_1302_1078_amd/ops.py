@@ -1,0 +1,287 @@
+"""Python binding of the CSR library: argument marshalling only.
+
+Every operation here calls one C entry point of libspx.so on the caller's
+current torch stream; all arithmetic runs in the library's HIP kernels.
+PyTorch provides device memory (tensors) and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import PlanOpts, check
+
+_DT = {torch.float64: _lib.SPX_F64, torch.float32: _lib.SPX_F32, torch.bfloat16: _lib.SPX_BF16}
+
+
+def dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DT[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}") from None
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU (no CPU path)")
+
+
+def _contig(*ts):
+    for t in ts:
+        if t is not None and not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class CSR:
+    """CSR matrix on the device: rowptr int32[m+1], colind int32[nnz], values[nnz]."""
+    rowptr: torch.Tensor
+    colind: torch.Tensor
+    values: torch.Tensor
+    shape: tuple
+
+    @property
+    def m(self) -> int:
+        return int(self.shape[0])
+
+    @property
+    def n(self) -> int:
+        return int(self.shape[1])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colind.numel())
+
+    @property
+    def device(self):
+        return self.rowptr.device
+
+    def with_values(self, values: torch.Tensor) -> "CSR":
+        if values.numel() != self.nnz:
+            raise ValueError("values length differs from nnz")
+        return CSR(self.rowptr, self.colind, values, self.shape)
+
+
+def version() -> str:
+    return _lib.load().spx_version().decode()
+
+
+def default_opts(k: int = 1, vtype=torch.float64) -> PlanOpts:
+    o = PlanOpts()
+    code = vtype if isinstance(vtype, int) else _DT[vtype]
+    check(_lib.load().spx_plan_default_opts(k, code, ctypes.byref(o)), "spx_plan_default_opts")
+    return o
+
+
+# ---------------------------------------------------------------- assembly and validation
+
+def from_coo(m: int, n: int, r: torch.Tensor, c: torch.Tensor, v: torch.Tensor) -> CSR:
+    """Canonical CSR from triplets (device int32 r, c and float64 v)."""
+    L = _lib.load()
+    _dev(r, c, v)
+    _contig(r, c, v)
+    if r.dtype != torch.int32 or c.dtype != torch.int32 or v.dtype != torch.float64:
+        raise TypeError("r, c must be int32 and v float64")
+    nnz_in = int(r.numel())
+    dev = r.device
+    ws_bytes = ctypes.c_size_t()
+    check(L.csr_from_coo_workspace_bytes(m, n, nnz_in, ctypes.byref(ws_bytes)), "csr_from_coo")
+    ws = _workspace(ws_bytes.value, dev)
+    rowptr = torch.empty(m + 1, dtype=torch.int32, device=dev)
+    colind = torch.empty(max(nnz_in, 1), dtype=torch.int32, device=dev)
+    values = torch.empty(max(nnz_in, 1), dtype=torch.float64, device=dev)
+    nnz_out = torch.empty(1, dtype=torch.int32, device=dev)
+    check(L.csr_from_coo(m, n, nnz_in, _ptr(r), _ptr(c), _ptr(v), _ptr(rowptr), _ptr(colind),
+                         _ptr(values), _ptr(nnz_out), _ptr(ws), ws_bytes.value, _stream()),
+          "csr_from_coo")
+    t = int(nnz_out.item())
+    if t < 0:
+        raise ValueError("csr_from_coo: a triplet index is out of range")
+    return CSR(rowptr, colind[:t], values[:t], (m, n))
+
+
+def validate(A: CSR, check_sorted: bool = True) -> int:
+    L = _lib.load()
+    status = torch.empty(1, dtype=torch.int32, device=A.device)
+    check(L.csr_validate(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), int(check_sorted),
+                         _ptr(status), _stream()), "csr_validate")
+    return int(status.item())
+
+
+# ---------------------------------------------------------------- plans
+
+class Plan:
+    """Row-binning plan of one sparsity pattern; owns its device workspace."""
+
+    def __init__(self, rowptr: torch.Tensor, m: int, n: int, nnz: int, opts: PlanOpts | None = None):
+        L = _lib.load()
+        _dev(rowptr)
+        self.opts = opts if opts is not None else default_opts(1)
+        self.m, self.n, self.nnz = m, n, nnz
+        nb = ctypes.c_size_t()
+        check(L.csr_plan_workspace_bytes(m, nnz, ctypes.byref(self.opts), ctypes.byref(nb)),
+              "csr_plan_workspace_bytes")
+        self.workspace = _workspace(nb.value, rowptr.device)
+        h = ctypes.c_void_p()
+        check(L.csr_plan_create(m, n, nnz, _ptr(rowptr), ctypes.byref(self.opts), _ptr(self.workspace),
+                                nb.value, _stream(), ctypes.byref(h)), "csr_plan_create")
+        self.handle = h
+
+    @classmethod
+    def for_matrix(cls, A: CSR, opts: PlanOpts | None = None, k: int = 1) -> "Plan":
+        return cls(A.rowptr, A.m, A.n, A.nnz, opts if opts is not None else default_opts(k, A.values.dtype))
+
+    def export_bins(self):
+        import numpy as np
+        nb = self.opts.nbins
+        perm = np.empty(max(self.m, 1), dtype=np.int32)
+        off = np.empty(nb + 1, dtype=np.int32)
+        check(_lib.load().csr_plan_export_bins(self.handle, perm.ctypes.data_as(ctypes.c_void_p),
+                                               off.ctypes.data_as(ctypes.c_void_p)), "export_bins")
+        return perm[:self.m], off
+
+    def info(self) -> dict:
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().csr_plan_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "csr_plan_info")
+        return {"nbins": a.value, "split_rows": b.value, "segments": c.value}
+
+    @property
+    def ptr(self):
+        return self.handle
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.csr_plan_destroy(h)
+            self.handle = None
+
+
+def _plan_ptr(plan):
+    return plan.handle if plan is not None else ctypes.c_void_p(0)
+
+
+# ---------------------------------------------------------------- products
+
+def spmv(A: CSR, x: torch.Tensor, y: torch.Tensor | None = None, plan: Plan | None = None) -> torch.Tensor:
+    """y <- A x."""
+    L = _lib.load()
+    _dev(A.rowptr, x)
+    _contig(x)
+    if x.numel() < A.n:
+        raise ValueError(f"x has {x.numel()} entries, A has {A.n} columns")
+    if y is None:
+        y = torch.empty(A.m, dtype=x.dtype, device=x.device)
+    _contig(y)
+    if y.numel() < A.m or y.dtype != x.dtype:
+        raise ValueError("y must hold m entries of x's dtype")
+    check(L.csr_spmv(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(A.values),
+                     dtype_code(A.values), _ptr(x), _ptr(y), dtype_code(x), _plan_ptr(plan), _stream()),
+          "csr_spmv")
+    return y
+
+
+def spmm(A: CSR, X: torch.Tensor, Y: torch.Tensor | None = None, plan: Plan | None = None) -> torch.Tensor:
+    """Y <- A X with X (n x k) and Y (m x k) row-major (unit column stride)."""
+    L = _lib.load()
+    _dev(A.rowptr, X)
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be 2-D with unit column stride")
+    k = X.shape[1]
+    if X.shape[0] < A.n:
+        raise ValueError(f"X has {X.shape[0]} rows, A has {A.n} columns")
+    if Y is None:
+        Y = torch.empty((A.m, k), dtype=X.dtype, device=X.device)
+    if Y.dim() != 2 or Y.stride(1) != 1 or Y.shape[0] < A.m or Y.shape[1] != k or Y.dtype != X.dtype:
+        raise ValueError("Y must be m x k with unit column stride and X's dtype")
+    check(L.csr_spmm(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(A.values),
+                     dtype_code(A.values), k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), dtype_code(X),
+                     _plan_ptr(plan), _stream()), "csr_spmm")
+    return Y
+
+
+# ---------------------------------------------------------------- transpose and gradients
+
+@dataclass
+class CSCIndex:
+    colptr: torch.Tensor
+    rowind: torch.Tensor
+    perm: torch.Tensor
+
+
+def transpose_index(A: CSR) -> CSCIndex:
+    L = _lib.load()
+    dev = A.device
+    nb = ctypes.c_size_t()
+    check(L.csr_transpose_index_workspace_bytes(A.m, A.n, A.nnz, ctypes.byref(nb)), "transpose_index")
+    ws = _workspace(nb.value, dev)
+    colptr = torch.empty(A.n + 1, dtype=torch.int32, device=dev)
+    rowind = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    perm = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    check(L.csr_transpose_index(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(colptr),
+                                _ptr(rowind), _ptr(perm), _ptr(ws), nb.value, _stream()),
+          "csr_transpose_index")
+    return CSCIndex(colptr, rowind[:A.nnz], perm[:A.nnz])
+
+
+def spmv_t(A: CSR, dY: torch.Tensor, mode: int = 0, index: CSCIndex | None = None,
+           plan: Plan | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """dX <- A^T dY.  mode 0: deterministic gather over the CSC index (plan, if
+    given, is a plan of the CSC pattern); mode 1: atomic scatter (plan of the
+    CSR pattern)."""
+    L = _lib.load()
+    _dev(A.rowptr, dY)
+    vec = dY.dim() == 1
+    k = 1 if vec else dY.shape[1]
+    if dY.shape[0] < A.m or (not vec and dY.stride(1) != 1) or (vec and not dY.is_contiguous()):
+        raise ValueError("dY must have m rows and unit column stride")
+    if out is None:
+        out = torch.empty((A.n,) if vec else (A.n, k), dtype=dY.dtype, device=dY.device)
+    if out.shape[0] < A.n or out.dim() != dY.dim() or (not vec and out.stride(1) != 1):
+        raise ValueError("out must have n rows and unit column stride")
+    lddy = 1 if vec else dY.stride(0)
+    lddx = 1 if vec else out.stride(0)
+    if mode == 0 and index is None:
+        index = transpose_index(A)
+    cp, ri, pm = (index.colptr, index.rowind, index.perm) if index is not None else (None, None, None)
+    check(L.csr_spmv_t(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(cp), _ptr(ri), _ptr(pm),
+                       _ptr(A.values), dtype_code(A.values), k, _ptr(dY), lddy, _ptr(out), lddx,
+                       dtype_code(dY), mode, _plan_ptr(plan), _stream()), "csr_spmv_t")
+    return out
+
+
+def sddmm(A: CSR, dY: torch.Tensor, X: torch.Tensor, plan: Plan | None = None,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """out[p] = dY[row(p), :] . X[colind[p], :] for each stored nonzero p."""
+    L = _lib.load()
+    _dev(A.rowptr, dY, X)
+    vec = dY.dim() == 1
+    k = 1 if vec else dY.shape[1]
+    if dY.shape[0] < A.m or X.shape[0] < A.n or X.dim() != dY.dim() or X.dtype != dY.dtype:
+        raise ValueError("dY must have m rows and X n rows, same rank and dtype")
+    if not vec and (X.shape[1] != k or dY.stride(1) != 1 or X.stride(1) != 1):
+        raise ValueError("dY and X must be k wide with unit column stride")
+    if out is None:
+        out = torch.empty(A.nnz, dtype=dY.dtype, device=dY.device)
+    if out.numel() < A.nnz or not out.is_contiguous():
+        raise ValueError("out must hold nnz entries")
+    check(L.csr_sddmm(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), k, _ptr(dY),
+                      1 if vec else dY.stride(0), _ptr(X), 1 if vec else X.stride(0), _ptr(out),
+                      dtype_code(dY), _plan_ptr(plan), _stream()), "csr_sddmm")
+    return out

@@ -1,0 +1,96 @@
+"""CPU-side checks of the C ABI library: it loads, exports every function that
+include/spx.h declares, rejects bad arguments before touching the GPU, and the
+Python layer fails loudly when the library is missing."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "spx.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1302_1078_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1302_1078_amd import build
+        build.build()
+    return _lib.load()
+
+
+def test_header_lists_the_entry_points():
+    names = header_functions()
+    for must in ("csr_spmv", "csr_spmm", "csr_from_coo", "csr_plan_create", "csr_spmv_t", "csr_sddmm",
+                 "csr_transpose_index", "csr_batch_create", "csr_batch_run", "spx_last_error"):
+        assert must in names
+    assert len(names) >= 22
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1302_1078_amd import _lib
+    for name in header_functions():
+        assert getattr(lib, name, None) is not None, name
+    assert set(header_functions()) == set(_lib.SIGNATURES)
+
+
+def test_argument_errors_without_gpu(lib):
+    from paper_1302_1078_amd import _lib
+    o = _lib.PlanOpts()
+    assert lib.spx_plan_default_opts(0, 0, ctypes.byref(o)) == _lib.SPX_ERR_INVALID
+    assert b"k=0" in lib.spx_last_error()
+    assert lib.spx_plan_default_opts(16, 0, ctypes.byref(o)) == _lib.SPX_OK and o.max_k == 16
+    nb = ctypes.c_size_t()
+    bad = _lib.PlanOpts.from_dict({"nbins": 3, "upper": [8, 4], "lanes": [1, 2, 4]})
+    assert lib.csr_plan_workspace_bytes(10, 10, ctypes.byref(bad), ctypes.byref(nb)) == _lib.SPX_ERR_INVALID
+    bad = _lib.PlanOpts.from_dict({"nbins": 2, "upper": [8], "lanes": [0, 4]})
+    assert lib.csr_plan_workspace_bytes(10, 10, ctypes.byref(bad), ctypes.byref(nb)) == _lib.SPX_ERR_INVALID
+    bad = _lib.PlanOpts.from_dict({"nbins": 1, "upper": [], "lanes": [128]})
+    assert lib.csr_plan_workspace_bytes(10, 10, ctypes.byref(bad), ctypes.byref(nb)) == _lib.SPX_ERR_INVALID
+    good = _lib.PlanOpts.from_dict({"nbins": 2, "upper": [8], "lanes": [4, 0], "split_chunk": 512})
+    assert lib.csr_plan_workspace_bytes(1000, 9000, ctypes.byref(good), ctypes.byref(nb)) == _lib.SPX_OK
+    assert nb.value >= 4 * 1000
+    # sizes and dtype pairs are checked before any launch
+    null = ctypes.c_void_p(0)
+    assert lib.csr_spmv(-1, 4, 0, null, null, null, 0, null, null, 0, null, null) == _lib.SPX_ERR_INVALID
+    assert lib.csr_spmv(4, 4, 0, null, null, null, 0, null, null, 1, null, null) == _lib.SPX_ERR_UNSUPPORTED
+    assert lib.csr_spmv(0, 4, 0, null, null, null, 0, null, null, 0, null, null) == _lib.SPX_OK
+    assert lib.csr_spmm(4, 4, 0, null, null, null, 0, 8, null, 4, null, 8, 0, null, null) == _lib.SPX_ERR_INVALID
+    assert lib.csr_spmv_t(4, 4, 1, null, null, null, null, null, null, 0, 1, null, 1, null, 1, 0, 0, null,
+                          null) == _lib.SPX_ERR_INVALID
+    assert lib.csr_from_coo_workspace_bytes(4, 4, -1, ctypes.byref(nb)) == _lib.SPX_ERR_INVALID
+    assert lib.csr_from_coo(4, 4, 2, null, null, null, null, null, null, null, null, 0, null) == _lib.SPX_ERR_INVALID
+    assert b"gfx950" in lib.spx_version()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    code = ("import paper_1302_1078_amd._lib as L; L.LIB_PATH = '/nonexistent/libspx.so'; L._lib = None\n"
+            "import paper_1302_1078_amd as P\n"
+            "try:\n    P.version()\nexcept ImportError as e:\n    print('LOUD', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert "LOUD" in r.stdout, r.stderr
+
+
+def test_plan_opts_roundtrip_and_autotune_cache(tmp_path):
+    from paper_1302_1078_amd import _lib, autotune
+    d = {"nbins": 3, "upper": [4, 64], "lanes": [4, 64, 0], "split_chunk": 1024, "kahan_len": 256,
+         "max_k": 8, "flags": 0}
+    assert _lib.PlanOpts.from_dict(d).to_dict() == d
+    p = tmp_path / "c.json"
+    p.write_text("{broken")
+    assert autotune.load_cache(str(p)) == {}
+    p.write_text("[1, 2]")
+    assert autotune.load_cache(str(p)) == {}
+    assert autotune._valid({"opts": {"nbins": 2, "upper": [3], "lanes": [1]}}) is None
+    assert autotune._valid({"opts": d}) is not None
+    assert autotune._valid({"nope": 1}) is None

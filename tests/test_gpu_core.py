@@ -1,0 +1,270 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Bars: integer/index work bit-exact; FP64 products rel2 <= 1e-12 (2-norm,
+per column); exact-arithmetic inputs bit-exact under any summation order;
+every plan variant (each lane width, split rows) deterministic run to run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import spgen
+from _cases import KINDS, int_valued, matrix, single_bin_opts, to_gpu, two_bin_opts
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def spx():
+    import paper_1302_1078_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def dev_vec(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    return t.to(dtype) if dtype is not None else t
+
+
+def plan_variants(spx, A, k=1):
+    """(name, plan) pairs: none, default, and one plan per lane width."""
+    G = to_gpu(A)
+    out = [("none", None), ("default", spx.Plan.for_matrix(G, spx.default_opts(k)))]
+    for lanes in (1, 2, 4, 8, 16, 32, 64, 256):
+        out.append((f"lanes{lanes}", spx.Plan.for_matrix(G, single_bin_opts(lanes, k))))
+    out.append(("split", spx.Plan.for_matrix(G, single_bin_opts(0, k, chunk=256))))
+    out.append(("lanes8+split", spx.Plan.for_matrix(G, two_bin_opts(300, 8, k, chunk=256))))
+    return G, out
+
+
+# ---------------------------------------------------------------- assembly and validation
+
+@pytest.mark.parametrize("kind", ["powerlaw", "stencil27", "empty_rows", "tall", "wide"])
+def test_from_coo_bit_exact(spx, torch, kind):
+    A = matrix(kind, seed=1)
+    coo = spgen.COO(A.m, A.n, A.row_of(), A.colind, A.values)
+    # add duplicates of a random tenth of the entries, then shuffle
+    rng = np.random.default_rng(3)
+    d = rng.choice(A.nnz, A.nnz // 10, replace=False)
+    coo = spgen.COO(A.m, A.n, np.concatenate([coo.r, coo.r[d]]), np.concatenate([coo.c, coo.c[d]]),
+                    np.concatenate([coo.v, rng.uniform(-1, 1, d.size)]))
+    coo = spgen.shuffled(coo, seed=5)
+    ref = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = spx.from_coo(coo.m, coo.n, dev_vec(torch, coo.r), dev_vec(torch, coo.c), dev_vec(torch, coo.v))
+    assert np.array_equal(G.rowptr.cpu().numpy(), ref.rowptr)
+    assert np.array_equal(G.colind.cpu().numpy(), ref.colind)
+    assert np.array_equal(G.values.cpu().numpy().view(np.uint64), ref.values.view(np.uint64))
+
+
+def test_from_coo_edge_cases(spx, torch):
+    e = lambda a, dt: dev_vec(torch, np.asarray(a, dtype=dt))  # noqa: E731
+    G = spx.from_coo(4, 3, e([], np.int32), e([], np.int32), e([], np.float64))
+    assert G.nnz == 0 and G.rowptr.cpu().tolist() == [0, 0, 0, 0, 0]
+    G = spx.from_coo(1, 1, e([0, 0], np.int32), e([0, 0], np.int32), e([2.0, 3.0], np.float64))
+    assert G.rowptr.cpu().tolist() == [0, 1] and G.values.cpu().tolist() == [5.0]
+    # input-order duplicate sum: (1e16 + 1) - 1e16 = 0 in FP64
+    G = spx.from_coo(1, 3, e([0, 0, 0], np.int32), e([2, 2, 2], np.int32), e([1e16, 1.0, -1e16], np.float64))
+    assert G.values.cpu().tolist() == [0.0]
+    with pytest.raises(ValueError):
+        spx.from_coo(2, 2, e([0, 2], np.int32), e([0, 0], np.int32), e([1.0, 1.0], np.float64))
+
+
+def test_validate_codes(spx, torch):
+    A = matrix("powerlaw", 2)
+    G = to_gpu(A)
+    assert spx.validate(G) == 0
+    rp = A.rowptr.copy()
+    rp[-1] += 1
+    assert spx.validate(spx.CSR(dev_vec(torch, rp), G.colind, G.values, G.shape)) != 0
+    rp = A.rowptr.copy()
+    rp[5], rp[6] = rp[6] + 3, rp[5]
+    assert spx.validate(spx.CSR(dev_vec(torch, rp), G.colind, G.values, G.shape)) == 3
+    ci = A.colind.copy()
+    ci[7] = A.n
+    assert spx.validate(spx.CSR(G.rowptr, dev_vec(torch, ci), G.values, G.shape)) == 2
+    L = A.row_lengths()
+    i = int(np.argmax(L))
+    ci = A.colind.copy()
+    ci[A.rowptr[i]], ci[A.rowptr[i] + 1] = ci[A.rowptr[i] + 1], ci[A.rowptr[i]]
+    bad = spx.CSR(G.rowptr, dev_vec(torch, ci), G.values, G.shape)
+    assert spx.validate(bad, check_sorted=True) == 1 and spx.validate(bad, check_sorted=False) == 0
+
+
+# ---------------------------------------------------------------- plans
+
+@pytest.mark.parametrize("kind", ["powerlaw", "stencil27", "empty_rows", "one_long_row"])
+@pytest.mark.parametrize("which", ["spmv", "spmm16", "custom"])
+def test_plan_bins_bit_exact(spx, kind, which):
+    A = matrix(kind, seed=4)
+    G = to_gpu(A)
+    if which == "spmv":
+        o = spx.default_opts(1)
+    elif which == "spmm16":
+        o = spx.default_opts(16)
+    else:
+        o = two_bin_opts(5, 4, chunk=300)
+    plan = spx.Plan.for_matrix(G, o)
+    perm, off = plan.export_bins()
+    nb = o.nbins
+    ref_perm, ref_off = oracle.bin_rows(A.rowptr, list(o.upper[:nb]))
+    assert np.array_equal(perm, ref_perm) and np.array_equal(off, ref_off)
+    info = plan.info()
+    if o.lanes[nb - 1] == 0:
+        rows = ref_perm[ref_off[nb - 1]:ref_off[nb]]
+        L = A.row_lengths()[rows]
+        assert info["split_rows"] == rows.size
+        assert info["segments"] == int(np.maximum(1, -(-L // o.split_chunk)).sum())
+
+
+# ---------------------------------------------------------------- SpMV FP64
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_spmv_f64_parity_all_plans(spx, torch, kind):
+    A = matrix(kind, seed=7)
+    x = spgen.uniform(A.n, 11)
+    ref = oracle.spmv(A, x)
+    G, plans = plan_variants(spx, A)
+    xd = dev_vec(torch, x)
+    for name, plan in plans:
+        y = spx.spmv(G, xd, plan=plan).cpu().numpy()
+        assert oracle.rel2(y, ref) <= TOL_F64, (kind, name)
+        # per-row bound: any summation order of L products, FMA or not
+        bound = 2 * (A.row_lengths() + 2) * 2.0 ** -53 * oracle.spmv_abs(A, x)
+        assert (np.abs(y - ref) <= bound).all(), (kind, name)
+        empty = A.row_lengths() == 0
+        assert not np.signbit(y[empty]).any()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_spmv_exact_inputs_bit_exact(spx, torch, kind):
+    A = int_valued(matrix(kind, seed=8), seed=2)
+    x = spgen.small_ints(A.n, 3)
+    ref = oracle.spmv(A, x)
+    G, plans = plan_variants(spx, A)
+    xd = dev_vec(torch, x)
+    for name, plan in plans:
+        y = spx.spmv(G, xd, plan=plan).cpu().numpy()
+        assert np.array_equal(y, ref), (kind, name)
+
+
+def test_spmv_identity_permutation_laplacian(spx, torch):
+    n = 5000
+    x = spgen.uniform(n, 1)
+    perm = np.random.default_rng(0).permutation(n)
+    P = oracle.csr_from_coo(n, n, np.arange(n), perm, np.ones(n))
+    G = to_gpu(P)
+    y = spx.spmv(G, dev_vec(torch, x), plan=spx.Plan.for_matrix(G)).cpu().numpy()
+    assert np.array_equal(y, x[perm])
+    coo = spgen.stencil3d(20, 20, 20, 27, values="laplacian")
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = to_gpu(A)
+    y = spx.spmv(G, dev_vec(torch, np.ones(A.n)), plan=spx.Plan.for_matrix(G)).cpu().numpy()
+    assert np.array_equal(y, 26.0 - (A.row_lengths() - 1))
+
+
+def test_spmv_deterministic(spx, torch):
+    A = matrix("powerlaw_sq", seed=9)
+    G = to_gpu(A)
+    xd = dev_vec(torch, spgen.uniform(A.n, 2))
+    for o in (spx.default_opts(1), single_bin_opts(0, chunk=256)):
+        plan = spx.Plan.for_matrix(G, o)
+        ys = [spx.spmv(G, xd, plan=plan).cpu().numpy().view(np.uint64) for _ in range(4)]
+        assert all(np.array_equal(ys[0], y) for y in ys[1:])
+
+
+def test_degenerate_shapes(spx, torch):
+    # m == 0: no-op; n == 0 / nnz == 0: y = +0
+    Z = oracle.csr_from_coo(0, 5, [], [], [])
+    G = to_gpu(Z)
+    y = spx.spmv(G, dev_vec(torch, np.ones(5)))
+    assert y.numel() == 0
+    E = oracle.csr_from_coo(7, 0, [], [], [])
+    G = to_gpu(E)
+    for plan in (None, spx.Plan.for_matrix(G)):
+        y = torch.full((7,), float("nan"), dtype=torch.float64, device="cuda:0")
+        spx.spmv(G, torch.empty(0, dtype=torch.float64, device="cuda:0"), y=y, plan=plan)
+        yc = y.cpu().numpy()
+        assert (yc == 0).all() and not np.signbit(yc).any()
+        Y = torch.full((7, 4), float("nan"), dtype=torch.float64, device="cuda:0")
+        spx.spmm(G, torch.empty((0, 4), dtype=torch.float64, device="cuda:0"), Y=Y, plan=None)
+        assert (Y.cpu().numpy() == 0).all()
+
+
+def test_argument_errors(spx, torch):
+    A = matrix("uniform", 1)
+    G = to_gpu(A)
+    x = dev_vec(torch, np.ones(A.n))
+    with pytest.raises(spx.SpxError):
+        spx.spmv(G, x.float())  # (F64 values, F32 vectors) is not a supported pair
+    with pytest.raises(spx.SpxError):
+        spx.spmm(G, torch.ones((A.n, 0), dtype=torch.float64, device="cuda:0"))
+    other = spx.Plan.for_matrix(to_gpu(matrix("stencil5", 1)))
+    with pytest.raises(spx.SpxError):
+        spx.spmv(G, x, plan=other)
+    plan16 = spx.Plan.for_matrix(G, single_bin_opts(0, k=4, chunk=256))
+    with pytest.raises(spx.SpxError):
+        spx.spmm(G, torch.ones((A.n, 8), dtype=torch.float64, device="cuda:0"), plan=plan16)
+
+
+# ---------------------------------------------------------------- SpMM FP64
+
+@pytest.mark.parametrize("kind", ["powerlaw", "stencil27", "empty_rows", "one_long_row", "wide"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 8, 16, 32, 40, 100])
+def test_spmm_f64_parity(spx, torch, kind, k):
+    A = matrix(kind, seed=12)
+    X = spgen.uniform(A.n * k, 13).reshape(A.n, k)
+    ref = oracle.spmm(A, X)
+    G = to_gpu(A)
+    plans = [None, spx.Plan.for_matrix(G, spx.default_opts(k)),
+             spx.Plan.for_matrix(G, two_bin_opts(64, 64, k, chunk=256))]
+    for ld_pad in (0, 3):
+        Xd = torch.zeros((A.n, k + ld_pad), dtype=torch.float64, device="cuda:0")
+        Xd[:, :k] = dev_vec(torch, X)
+        Xv = Xd[:, :k]
+        for plan in plans:
+            Yd = torch.full((A.m, k + ld_pad), 7.0, dtype=torch.float64, device="cuda:0")
+            spx.spmm(G, Xv, Y=Yd[:, :k], plan=plan)
+            Y = Yd.cpu().numpy()
+            for j in range(k):
+                assert oracle.rel2(Y[:, j], ref[:, j]) <= TOL_F64, (kind, k, ld_pad, j)
+            if ld_pad:
+                assert (Y[:, k:] == 7.0).all()  # padding untouched
+
+
+@pytest.mark.parametrize("k", [4, 16])
+def test_spmm_exact_inputs_bit_exact(spx, torch, k):
+    A = int_valued(matrix("powerlaw", 5), 1)
+    X = spgen.small_ints(A.n * k, 6).reshape(A.n, k)
+    ref = oracle.spmm(A, X)
+    G = to_gpu(A)
+    for plan in (None, spx.Plan.for_matrix(G, spx.default_opts(k)),
+                 spx.Plan.for_matrix(G, single_bin_opts(0, k, chunk=256))):
+        Y = spx.spmm(G, dev_vec(torch, X), plan=plan).cpu().numpy()
+        assert np.array_equal(Y, ref)
+
+
+def test_spmm_k1_equals_spmv_bitwise(spx, torch):
+    A = matrix("powerlaw_sq", 3)
+    G = to_gpu(A)
+    x = spgen.uniform(A.n, 4)
+    plan = spx.Plan.for_matrix(G, spx.default_opts(1))
+    y = spx.spmv(G, dev_vec(torch, x), plan=plan).cpu().numpy()
+    Y = spx.spmm(G, dev_vec(torch, x.reshape(-1, 1)), plan=plan).cpu().numpy()
+    assert np.array_equal(y.view(np.uint64), Y[:, 0].view(np.uint64))
+
+
+def test_spmm_deterministic_split(spx, torch):
+    A = matrix("one_long_row", 3)
+    G = to_gpu(A)
+    X = dev_vec(torch, spgen.uniform(A.n * 16, 4).reshape(A.n, 16))
+    plan = spx.Plan.for_matrix(G, spx.default_opts(16))
+    assert plan.info()["segments"] > 1
+    Ys = [spx.spmm(G, X, plan=plan).cpu().numpy().view(np.uint64) for _ in range(4)]
+    assert all(np.array_equal(Ys[0], Y) for Y in Ys[1:])

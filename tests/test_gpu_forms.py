@@ -1,0 +1,260 @@
+"""GPU parity of the precision and differentiation forms against the oracle.
+
+Precision: FP32/BF16 values with FP32 vectors.  The accumulation error is
+measured against the oracle on the stored (quantised) inputs widened exactly
+to FP64; every row must satisfy a floating-point error bound
+(Higham, Accuracy and Stability of Numerical Algorithms, 2nd ed., Ch. 3-4;
+Ogita, Rump and Oishi, SIAM J. Sci. Comput. 26(6), 2005, for the compensated
+dot product):
+  plain FP32 rows:        |e_i| <= gamma_{L+8}(2^-24) * sum_p |a_p x_p|
+  compensated long rows:  |e_i| <= 2^-24 |y_i| + (gamma_L(2^-24))^2 * S_i + 2^-45 S_i
+The total error against the original FP64 data is reported (rel2).
+
+Differentiation: transpose products, sampled dot and the autograd Function.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import spgen
+from _cases import gamma, int_valued, matrix, single_bin_opts, to_gpu, two_bin_opts
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def spx():
+    import paper_1302_1078_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def quantised(A, vdtype, torch):
+    """(GPU CSR with stored values, FP64 widening of the stored values)."""
+    if vdtype == "f32":
+        q = spgen.to_f32(A.values)
+        vals = dev(torch, q)
+        wide = q.astype(np.float64)
+    else:
+        bits = spgen.to_bf16_bits(A.values)
+        vals = dev(torch, bits.view(np.int16)).view(torch.bfloat16)
+        wide = spgen.bf16_bits_to_f64(bits)
+    import paper_1302_1078_amd as spx
+    G = spx.CSR(dev(torch, A.rowptr), dev(torch, A.colind), vals, (A.m, A.n))
+    return G, oracle.CSR(A.m, A.n, A.rowptr, A.colind, wide)
+
+
+def check_bound(y, y5, S, L, kahan_len, what):
+    err = np.abs(y.astype(np.float64) - y5)
+    comp = L > kahan_len
+    plain_bound = gamma(L + 8, U32) * S
+    comp_bound = U32 * np.abs(y5) + gamma(L, U32) ** 2 * S + 2.0 ** -45 * S
+    assert (err[~comp] <= plain_bound[~comp]).all(), (what, "plain rows")
+    assert (err[comp] <= comp_bound[comp]).all(), (what, "compensated rows")
+
+
+@pytest.mark.parametrize("kind", ["powerlaw", "one_long_row", "stencil27", "empty_rows"])
+@pytest.mark.parametrize("vdtype", ["f32", "bf16"])
+def test_precision_spmv_bounds(spx, torch, kind, vdtype):
+    A = matrix(kind, seed=21)
+    x = spgen.uniform(A.n, 22)
+    xq = spgen.to_f32(x)
+    G, A5 = quantised(A, vdtype, torch)
+    y5 = oracle.spmv(A5, xq.astype(np.float64))
+    S = oracle.spmv_abs(A5, xq.astype(np.float64))
+    y3 = oracle.spmv(A, x)
+    L = A.row_lengths()
+    for name, opts in [("default", spx.default_opts(1, torch.float32)),
+                       ("block", single_bin_opts(256)), ("split", single_bin_opts(0, chunk=256)),
+                       ("wave+split", two_bin_opts(300, 64, chunk=512))]:
+        plan = spx.Plan.for_matrix(G, opts)
+        y = spx.spmv(G, dev(torch, xq), plan=plan).cpu().numpy()
+        check_bound(y, y5, S, L, opts.kahan_len, (kind, vdtype, name))
+        total = oracle.rel2(y.astype(np.float64), y3)
+        assert total <= (2e-6 if vdtype == "f32" else 2e-2), (kind, vdtype, name, total)
+
+
+@pytest.mark.parametrize("vdtype", ["f32", "bf16"])
+@pytest.mark.parametrize("k", [8, 32])
+def test_precision_spmm_bounds(spx, torch, vdtype, k):
+    A = matrix("powerlaw", seed=23)
+    X = spgen.uniform(A.n * k, 24).reshape(A.n, k)
+    Xq = spgen.to_f32(X)
+    G, A5 = quantised(A, vdtype, torch)
+    Y5 = oracle.spmm(A5, Xq.astype(np.float64))
+    L = A.row_lengths()
+    plan = spx.Plan.for_matrix(G, spx.default_opts(k, torch.float32))
+    Y = spx.spmm(G, dev(torch, Xq), plan=plan).cpu().numpy()
+    for j in (0, k // 2, k - 1):
+        S = oracle.spmv_abs(A5, Xq[:, j].astype(np.float64))
+        check_bound(Y[:, j], Y5[:, j], S, L, 256, (vdtype, k, j))
+
+
+def test_compensated_sum_pin(spx, torch):
+    # 1.0 followed by 4096 copies of 2^-25 (exact sum 1 + 2^-13 = 1.0001220703125).
+    # With compensation the FP32 result is exact; without it the lane that holds
+    # 1.0 drops its small addends.
+    vals = np.array([1.0] + [2.0 ** -25] * 4096)
+    A = oracle.csr_from_coo(1, vals.size, np.zeros(vals.size), np.arange(vals.size), vals)
+    G = spx.CSR(dev(torch, A.rowptr), dev(torch, A.colind), dev(torch, vals.astype(np.float32)), (1, vals.size))
+    ones = torch.ones(vals.size, dtype=torch.float32, device="cuda:0")
+    exact = np.float32(1.0001220703125)
+    for opts in (single_bin_opts(256), single_bin_opts(0, chunk=1024), single_bin_opts(64)):
+        y = spx.spmv(G, ones, plan=spx.Plan.for_matrix(G, opts)).cpu().numpy()
+        assert y[0] == exact
+    opts = single_bin_opts(256, kahan=1_000_000)  # compensation off
+    y = spx.spmv(G, ones, plan=spx.Plan.for_matrix(G, opts)).cpu().numpy()
+    assert y[0] != exact and abs(float(y[0]) - 1.0001220703125) < 1e-6
+
+
+def test_bf16_exact_values(spx, torch):
+    # integers in [-8, 8] are exact in BF16; with integer x every sum is exact
+    A = int_valued(matrix("powerlaw", 25), 3)
+    x = spgen.small_ints(A.n, 4)
+    G, _ = quantised(A, "bf16", torch)
+    y = spx.spmv(G, dev(torch, x.astype(np.float32)), plan=spx.Plan.for_matrix(G)).cpu().numpy()
+    assert np.array_equal(y.astype(np.float64), oracle.spmv(A, x))
+
+
+# ---------------------------------------------------------------- transpose index and products
+
+@pytest.mark.parametrize("kind", ["powerlaw", "empty_rows", "tall", "wide"])
+def test_transpose_index_bit_exact(spx, torch, kind):
+    A = matrix(kind, 31)
+    G = to_gpu(A)
+    idx = spx.transpose_index(G)
+    perm = np.argsort(A.colind, kind="stable")
+    colptr = np.concatenate([[0], np.cumsum(np.bincount(A.colind, minlength=A.n))])
+    assert np.array_equal(idx.perm.cpu().numpy(), perm)
+    assert np.array_equal(idx.rowind.cpu().numpy(), A.row_of()[perm])
+    assert np.array_equal(idx.colptr.cpu().numpy(), colptr)
+
+
+@pytest.mark.parametrize("kind", ["powerlaw", "empty_rows", "tall", "wide", "one_long_row"])
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_spmv_t_parity(spx, torch, kind, k):
+    A = matrix(kind, 32)
+    G = to_gpu(A)
+    dY = spgen.normal(A.m * k, 33).reshape(A.m, k)
+    ref = oracle.spmv_t(A, dY)
+    idx = spx.transpose_index(G)
+    plan_t = spx.Plan(idx.colptr, A.n, A.m, A.nnz, spx.default_opts(k))
+    plan = spx.Plan.for_matrix(G, spx.default_opts(1))
+    dYd = dev(torch, dY if k > 1 else dY[:, 0])
+    outs = []
+    for mode, pl in ((0, None), (0, plan_t), (1, None), (1, plan)):
+        dX = spx.spmv_t(G, dYd, mode=mode, index=idx, plan=pl).cpu().numpy().reshape(A.n, k)
+        for j in range(k):
+            assert oracle.rel2(dX[:, j], ref[:, j]) <= 1e-12, (kind, k, mode, j)
+        outs.append(dX)
+    again = spx.spmv_t(G, dYd, mode=0, index=idx, plan=plan_t).cpu().numpy().reshape(A.n, k)
+    assert np.array_equal(outs[1].view(np.uint64), again.view(np.uint64))  # deterministic
+
+
+def test_spmv_t_exact_inputs_and_adjoint(spx, torch):
+    A = int_valued(matrix("powerlaw", 34), 1)
+    G = to_gpu(A)
+    dy = spgen.small_ints(A.m, 5)
+    ref = oracle.spmv_t(A, dy)
+    for mode in (0, 1):
+        assert np.array_equal(spx.spmv_t(G, dev(torch, dy), mode=mode).cpu().numpy(), ref)
+    B = matrix("powerlaw", 35)
+    G = to_gpu(B)
+    x, dy = spgen.uniform(B.n, 1), spgen.normal(B.m, 2)
+    atdy = spx.spmv_t(G, dev(torch, dy), mode=0).cpu().numpy()
+    ax = spx.spmv(G, dev(torch, x)).cpu().numpy()
+    scale = float(np.dot(np.abs(dy), oracle.spmv_abs(B, np.abs(x))))
+    assert abs(float(np.dot(atdy, x)) - float(np.dot(dy, ax))) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_sddmm_parity(spx, torch, k):
+    A = matrix("powerlaw", 36)
+    G = to_gpu(A)
+    dY = spgen.normal(A.m * k, 37).reshape(A.m, k)
+    X = spgen.uniform(A.n * k, 38).reshape(A.n, k)
+    ref = oracle.sddmm(A, dY, X)
+    for plan in (None, spx.Plan.for_matrix(G, spx.default_opts(1))):
+        if k == 1:
+            out = spx.sddmm(G, dev(torch, dY[:, 0]), dev(torch, X[:, 0]), plan=plan).cpu().numpy()
+            assert np.array_equal(out.view(np.uint64), ref.view(np.uint64))  # one rounded product
+        else:
+            out = spx.sddmm(G, dev(torch, dY), dev(torch, X), plan=plan).cpu().numpy()
+            scale = oracle.sddmm(A, np.abs(dY), np.abs(X))
+            assert (np.abs(out - ref) <= gamma(k + 1, 2.0 ** -53) * scale).all()
+    out32 = spx.sddmm(G, dev(torch, dY.astype(np.float32)), dev(torch, X.astype(np.float32))).cpu().numpy()
+    ref32 = oracle.sddmm(A, spgen.to_f32(dY).astype(np.float64), spgen.to_f32(X).astype(np.float64))
+    scale = oracle.sddmm(A, np.abs(dY), np.abs(X))
+    assert (np.abs(out32 - ref32) <= gamma(k + 1, U32) * scale * 1.01).all()
+
+
+# ---------------------------------------------------------------- autograd
+
+def test_autograd_gradcheck_f64(spx, torch):
+    coo = spgen.powerlaw(60, 50, 2.0, 40, 5.0, seed=3)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = to_gpu(A)
+    for mode in (0, 1):
+        g = spx.GradContext(G, mode=mode)
+        v = G.values.clone().requires_grad_(True)
+        x = dev(torch, spgen.uniform(A.n, 4)).requires_grad_(True)
+        assert torch.autograd.gradcheck(lambda vv, xx: spx.spmv_autograd(vv, xx, g), (v, x),
+                                        eps=1e-6, atol=1e-9, rtol=1e-7)
+        X = dev(torch, spgen.uniform(A.n * 3, 5).reshape(A.n, 3)).requires_grad_(True)
+        g3 = spx.GradContext(G, mode=mode, k=3)
+        assert torch.autograd.gradcheck(lambda vv, xx: spx.spmv_autograd(vv, xx, g3), (v, X),
+                                        eps=1e-6, atol=1e-9, rtol=1e-7)
+
+
+def test_autograd_dense_reference_and_fd_f32(spx, torch):
+    # 2,000-row submatrix of a Zipf(2.0) mean-20 matrix: the 10 longest rows
+    # plus 1,990 seeded rows, columns compacted to the ones touched.
+    coo = spgen.powerlaw(1 << 15, 1 << 15, 2.0, 20_000, 20.0, seed=0)
+    B = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    L = B.row_lengths()
+    longest = np.argsort(-L, kind="stable")[:10]
+    rest = np.setdiff1d(np.arange(B.m), longest)
+    rows = np.sort(np.concatenate([longest, np.random.default_rng(0).choice(rest, 1990, replace=False)]))
+    keep = np.isin(B.row_of(), rows)
+    r = np.searchsorted(rows, B.row_of()[keep])
+    cols, c = np.unique(B.colind[keep], return_inverse=True)
+    A = oracle.csr_from_coo(rows.size, cols.size, r, c, B.values[keep])
+    A32 = spx.CSR(dev(torch, A.rowptr), dev(torch, A.colind), dev(torch, spgen.to_f32(A.values)), (A.m, A.n))
+    x = spgen.to_f32(spgen.uniform(A.n, 7))
+    dy = spgen.to_f32(spgen.normal(A.m, 8))
+    g = spx.GradContext(A32, mode=0)
+    v = A32.values.clone().requires_grad_(True)
+    xt = dev(torch, x).requires_grad_(True)
+    y = spx.spmv_autograd(v, xt, g)
+    y.backward(dev(torch, dy))
+    # dense reference gradient (FP64 on the host)
+    D = np.zeros((A.m, A.n))
+    D[A.row_of(), A.colind] = spgen.to_f32(A.values)
+    assert np.allclose(xt.grad.cpu().numpy(), D.T @ dy, rtol=1e-5, atol=1e-5)
+    dv_ref = dy.astype(np.float64)[A.row_of()] * x.astype(np.float64)[A.colind]
+    assert np.allclose(v.grad.cpu().numpy(), dv_ref, rtol=1e-6, atol=1e-7)
+    # central differences with h = 1: y is bilinear, so there is no truncation error
+    f = lambda vv, xx: float(torch.dot(spx.spmv_autograd(vv, xx, g).double(), dev(torch, dy).double()))  # noqa: E731
+    rng = np.random.default_rng(1)
+    with torch.no_grad():
+        for p in list(rng.choice(A.nnz, 20, replace=False)) + [int(A.rowptr[A.m] - 1)]:
+            e = torch.zeros_like(v)
+            e[p] = 1.0
+            fd = (f(v + e, xt) - f(v - e, xt)) / 2.0
+            assert abs(fd - float(v.grad[p])) <= 1e-4 * (1 + abs(fd))
+        for j in rng.choice(A.n, 20, replace=False):
+            e = torch.zeros_like(xt)
+            e[j] = 1.0
+            fd = (f(v, xt + e) - f(v, xt - e)) / 2.0
+            assert abs(fd - float(xt.grad[j])) <= 1e-4 * (1 + abs(fd))
