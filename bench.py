@@ -1,21 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the CSR SpMV / SpMM hot path on one MI355X.
 
-Workload (default): the power-law matrix, 1,048,576 x 1,048,576 with
-Zipf(2.0) row lengths (mean 16, max 20,000) and hot columns of the same law,
-FP64 values, x and X uniform[-1, 1); one step = one SpMV y <- A x plus one
-SpMM Y <- A X with k = 16 (X, Y row-major).  CSR assembly and row binning run
-once before timing (the paper also leaves transformation time out).
+Headline workload: the power-law matrix, 1,048,576 x 1,048,576 with Zipf(2.0)
+row lengths (mean 16, max 20,000) and hot columns of the same law, FP64
+values, x and X uniform[-1, 1); one step = one SpMV y <- A x plus one SpMM
+Y <- A X with k = 16 (row-major).  CSR assembly and row binning run once,
+on the device, before timing (the paper also leaves transformation time
+out).  `value` is GFLOP/s of the step (2 tau (1 + k) flops per step).
 
-Protocol (the paper's Sec. 4): every timed run is preceded by a cache flush
-(a 1 GiB read-modify-write, outside the timed region, so A, x and X come from
-HBM and not from L2 or the 256 MB Infinity Cache); with the defaults
-(--warmup 10 --steps 60) that is 70 runs with the mean of the last 60.
-Kernel time is measured with HIP events on the stream the kernels run on.
+Protocol (the paper's Sec. 4): every timed call is preceded by a cache flush
+(a 1 GiB read-modify-write outside the timed region, so A, x and X come from
+HBM rather than from L2 or the 256 MB Infinity Cache); with the defaults
+(--warmup 10 --steps 60) that is 70 runs and the mean of the last 60.
+Kernel time comes from HIP events on the stream the kernels run on.
 
-Prints ONE JSON line.  `value` is GFLOP/s of the step (2 tau (1 + k) flops
-per step); the dominant kernel's effective HBM bandwidth (the paper's
-application bytes, Sec. 4.2 / Sec. 5) is reported against 8 TB/s.
+The other workloads are reported under detail.forms (skip with --quick):
+  c0  10,000 x 10,000, 10 uniform columns per row, FP64 SpMV (launch-bound)
+  c2  precision form: 27-point stencil on 128^3 and the power-law matrix,
+      FP64 / FP32 / BF16 values, k in {1, 8, 32}, error against the oracle
+  c3  differentiation form: 524,288 power-law (mean 20), FP32 forward and
+      backward (CSC-index and atomic transpose, sampled dot)
+  c4  batched form: 256 matrices in one persistent launch replayed from a
+      HIP graph, autotuned plans, against sequential single-matrix calls
 """
 from __future__ import annotations
 
@@ -43,21 +49,23 @@ def parse():
     ap.add_argument("--no-flush", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--forms", action="store_true", help="also time the FP32/BF16 forms on this matrix")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--forms", default="c0,c2,c3,c4", help="comma list of extra workloads")
+    ap.add_argument("--form-steps", type=int, default=20)
     return ap.parse_args()
 
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("product.hip", "device.hpp", "plan.hip"):
+    for name in ("product.hip", "product_impl.hpp", "device.hpp", "plan.hip"):
         with open(os.path.join(ROOT, "paper_1302_1078_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_key: str, launches_per_step: float):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or None
-    when the kernel sources changed since the counters were taken."""
+def traffic_for(kernel_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -71,6 +79,254 @@ def traffic_for(kernel_key: str, launches_per_step: float):
     except Exception:
         return None
 
+
+class Timer:
+    """Per-call HIP-event timing with an optional cache flush before each call."""
+
+    def __init__(self, torch, dev, flush: bool):
+        self.torch = torch
+        self.flush_buf = torch.zeros(1 << 27, dtype=torch.float64, device=dev) if flush else None
+
+    def run(self, fns, steps, warmup):
+        """fns: list of callables timed separately within each step.
+        Returns an array [steps, len(fns)] of seconds."""
+        import numpy as np
+        torch = self.torch
+        evs = []
+        for s in range(warmup + steps):
+            if self.flush_buf is not None:
+                self.flush_buf.add_(1.0)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(len(fns) + 1)]
+            e[0].record()
+            for i, fn in enumerate(fns):
+                fn()
+                e[i + 1].record()
+            if s >= warmup:
+                evs.append(e)
+        torch.cuda.synchronize()
+        return np.array([[e[i].elapsed_time(e[i + 1]) * 1e-3 for i in range(len(fns))] for e in evs])
+
+
+def app_bytes(m, n, nnz, k=1, sv=8, sx=8):
+    return (sv + 4) * nnz + sx * k * n + sx * k * m + 4 * (m + 1)
+
+
+def upload(torch, spx, coo, dev):
+    r = torch.from_numpy(coo.r).to(dev)
+    c = torch.from_numpy(coo.c).to(dev)
+    v = torch.from_numpy(coo.v).to(dev)
+    A = spx.from_coo(coo.m, coo.n, r, c, v)
+    del r, c, v
+    return A
+
+
+def oracle_of(A):
+    import oracle
+    return oracle.CSR(A.m, A.n, A.rowptr.cpu().numpy(), A.colind.cpu().numpy(),
+                      A.values.double().cpu().numpy())
+
+
+# ---------------------------------------------------------------- c0
+
+def bench_c0(ctx):
+    import numpy as np
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    A = upload(torch, spx, spgen.workload_c0(0), dev)
+    plan = spx.Plan.for_matrix(A)
+    x = torch.from_numpy(spgen.uniform(A.n, 0)).to(dev)
+    y = torch.empty(A.m, dtype=torch.float64, device=dev)
+    t = ctx["timer"].run([lambda: spx.spmv(A, x, y=y, plan=plan)], ctx["fsteps"], 5)[:, 0]
+    # a HIP graph of 100 back-to-back SpMVs (launch overhead amortised)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        spx.spmv(A, x, y=y, plan=plan)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(100):
+            spx.spmv(A, x, y=y, plan=plan)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    per = e0.elapsed_time(e1) * 1e-3 / 500
+    b = app_bytes(A.m, A.n, A.nnz)
+    return {"workload": "uniform 10,000 x 10,000, 10 nnz/row, FP64 SpMV", "nnz": A.nnz,
+            "us_single_flushed": float(t.mean() * 1e6), "us_per_spmv_graph100_warm": per * 1e6,
+            "gflops_graph": 2 * A.nnz / per / 1e9, "eff_gbs_graph": b / per / 1e9}
+
+
+# ---------------------------------------------------------------- c2
+
+def bench_c2(ctx, A1=None):
+    import numpy as np
+    import oracle
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    out = {}
+    mats = [("stencil27_128", upload(torch, spx, spgen.workload_c2_stencil(0), dev))]
+    if A1 is not None:
+        mats.append(("powerlaw_1M", A1))
+    for name, A in mats:
+        ref = oracle_of(A)
+        m, n, nnz = A.m, A.n, A.nnz
+        rows = {}
+        for k in (1, 8, 32):
+            X64 = spgen.uniform(n * k, 7, spgen.TAG_X).reshape(n, k)
+            Xq = spgen.to_f32(X64)
+            y3 = oracle.spmm(ref, X64) if k > 1 else oracle.spmv(ref, X64[:, 0])[:, None]
+            base_t = None
+            for vname in ("f64", "f32", "bf16"):
+                if vname == "f64":
+                    vals, Xd, wide_v, wide_x = A.values, torch.from_numpy(X64).to(dev), ref.values, X64
+                elif vname == "f32":
+                    vals = A.values.float()
+                    Xd = torch.from_numpy(Xq).to(dev)
+                    wide_v, wide_x = spgen.to_f32(ref.values).astype(np.float64), Xq.astype(np.float64)
+                else:
+                    vals = A.values.to(torch.bfloat16)
+                    Xd = torch.from_numpy(Xq).to(dev)
+                    wide_v = spgen.bf16_bits_to_f64(spgen.to_bf16_bits(ref.values))
+                    wide_x = Xq.astype(np.float64)
+                Aq = A.with_values(vals)
+                plan = spx.Plan.for_matrix(Aq, spx.default_opts(k, vals.dtype))
+                if k == 1:
+                    xd = Xd[:, 0].contiguous()
+                    yd = torch.empty(m, dtype=xd.dtype, device=dev)
+                    fn = lambda: spx.spmv(Aq, xd, y=yd, plan=plan)  # noqa: E731
+                else:
+                    yd = torch.empty((m, k), dtype=Xd.dtype, device=dev)
+                    fn = lambda: spx.spmm(Aq, Xd, Y=yd, plan=plan)  # noqa: E731
+                t = float(ctx["timer"].run([fn], ctx["fsteps"], 3)[:, 0].mean())
+                yh = yd.double().cpu().numpy().reshape(m, k)
+                sv = {"f64": 8, "f32": 4, "bf16": 2}[vname]
+                sx = 8 if vname == "f64" else 4
+                b = app_bytes(m, n, nnz, k, sv, sx)
+                r = {"us": t * 1e6, "gflops": 2 * nnz * k / t / 1e9, "eff_gbs": b / t / 1e9,
+                     "frac_hbm": b / t / 1e9 / PEAK_HBM_GBS, "bytes": b,
+                     "rel2_vs_fp64_oracle": max(oracle.rel2(yh[:, j], y3[:, j]) for j in range(k))}
+                if vname != "f64":
+                    A5 = oracle.CSR(m, n, ref.rowptr, ref.colind, wide_v)
+                    y5 = oracle.spmm(A5, wide_x) if k > 1 else oracle.spmv(A5, wide_x[:, 0])[:, None]
+                    r["rel2_vs_quantised_oracle"] = max(oracle.rel2(yh[:, j], y5[:, j]) for j in range(k))
+                    r["speedup_vs_f64"] = base_t / t
+                else:
+                    base_t = t
+                rows[f"k{k}_{vname}"] = r
+        out[name] = {"m": m, "nnz": nnz, "results": rows}
+        del ref
+    out["note"] = ("FP32/BF16 values with FP32 x/y and FP32 accumulation; rows longer than 256 use "
+                   "compensated sums with an FP64 cross-lane reduction")
+    return out
+
+
+# ---------------------------------------------------------------- c3
+
+def bench_c3(ctx):
+    import numpy as np
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    A64 = upload(torch, spx, spgen.workload_c3(0), dev)
+    A = A64.with_values(A64.values.float())
+    m, n, nnz = A.m, A.n, A.nnz
+    x = torch.from_numpy(spgen.to_f32(spgen.uniform(n, 3))).to(dev)
+    dy = torch.from_numpy(spgen.to_f32(spgen.normal(m, 4, spgen.TAG_DY))).to(dev)
+    g0 = spx.GradContext(A, mode=0)
+    plan = g0.plan
+    y = torch.empty(m, dtype=torch.float32, device=dev)
+    dx = torch.empty(n, dtype=torch.float32, device=dev)
+    dv = torch.empty(nnz, dtype=torch.float32, device=dev)
+    fns = [lambda: spx.spmv(A, x, y=y, plan=plan),
+           lambda: spx.spmv_t(A, dy, mode=0, index=g0.index, plan=g0.plan_t, out=dx),
+           lambda: spx.spmv_t(A, dy, mode=1, plan=plan, out=dx),
+           lambda: spx.sddmm(A, dy, x, plan=plan, out=dv)]
+    t = ctx["timer"].run(fns, ctx["fsteps"], 3).mean(axis=0)
+    fwd_b = app_bytes(m, n, nnz, 1, 4, 4)
+    csc_b = 4 * nnz * 3 + 4 * (n + 1) + 4 * m + 4 * n     # perm, rowind, values + colptr, dy, dx
+    atom_b = 8 * nnz + 4 * (m + 1) + 4 * m + 2 * 4 * n    # colind, values, rowptr, dy, dx zero+write
+    sdd_b = 8 * nnz + 4 * (m + 1) + 4 * m + 4 * n         # colind, out, rowptr, dy, x
+    # autograd round trip through the Function
+    v = A.values.clone().requires_grad_(True)
+    xt = x.clone().requires_grad_(True)
+
+    def step():
+        yy = spx.spmv_autograd(v, xt, g0)
+        yy.backward(dy)
+    ta = float(ctx["timer"].run([step], 10, 2)[:, 0].mean())
+    return {"workload": "power-law 524,288 x 524,288, Zipf(2.0) mean 20, FP32", "nnz": nnz,
+            "forward_us": t[0] * 1e6, "forward_eff_gbs": fwd_b / t[0] / 1e9,
+            "dx_csc_us": t[1] * 1e6, "dx_csc_eff_gbs": csc_b / t[1] / 1e9,
+            "dx_atomic_us": t[2] * 1e6, "dx_atomic_eff_gbs": atom_b / t[2] / 1e9,
+            "dvalues_us": t[3] * 1e6, "dvalues_eff_gbs": sdd_b / t[3] / 1e9,
+            "autograd_fwd_bwd_us": ta * 1e6,
+            "note": "gradients are checked in tests/test_gpu_forms.py (gradcheck, FD, dense reference)"}
+
+
+# ---------------------------------------------------------------- c4
+
+def bench_c4(ctx):
+    import numpy as np
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    from paper_1302_1078_amd import autotune
+    from paper_1302_1078_amd.batch import Batched
+    t0 = time.time()
+    specs = spgen.batch_specs(256, seed=0)
+    mats32, mats64, X32, X64, ks = [], [], [], [], []
+    flops = bytes32 = bytes64 = 0
+    for i, s in enumerate(specs):
+        A = upload(torch, spx, spgen.batch_matrix(s, 0, i), dev)
+        X = spgen.uniform(A.n * s.k, 1000 + i, spgen.TAG_X).reshape(A.n, s.k)
+        xd = torch.from_numpy(X[:, 0].copy() if s.k == 1 else X).to(dev)
+        mats64.append(A)
+        X64.append(xd)
+        mats32.append(A.with_values(A.values.float()))
+        X32.append(xd.float())
+        ks.append(s.k)
+        flops += 2 * A.nnz * s.k
+        bytes32 += app_bytes(A.m, A.n, A.nnz, s.k, 4, 4)
+        bytes64 += app_bytes(A.m, A.n, A.nnz, s.k, 8, 8)
+    gen_s = time.time() - t0
+    cache = os.path.join(ctx["tmp"], "autotune_c4.json")
+    t1 = time.time()
+    opts = [autotune.tune(A, X, reps=3, cache_path=cache)[0] for A, X in zip(mats32, X32)]
+    tune_s = time.time() - t1
+    B = Batched(mats32, X32, opts=opts)
+    g = B.capture()
+    t_graph = float(ctx["timer"].run([g.replay], ctx["fsteps"], 3)[:, 0].mean())
+    t_run = float(ctx["timer"].run([B.run], ctx["fsteps"], 3)[:, 0].mean())
+    plans32 = [spx.Plan.for_matrix(A, o) for A, o in zip(mats32, opts)]
+    plans64 = [spx.Plan.for_matrix(A, spx.default_opts(k)) for A, k in zip(mats64, ks)]
+    outs32 = [torch.empty_like(Y) for Y in B.Ys]
+    outs64 = [torch.empty(Y.shape, dtype=torch.float64, device=dev) for Y in B.Ys]
+
+    def seq(mats, Xs, plans, outs):
+        def f():
+            for A, X, p, Y in zip(mats, Xs, plans, outs):
+                if X.dim() == 1:
+                    spx.spmv(A, X, y=Y, plan=p)
+                else:
+                    spx.spmm(A, X, Y=Y, plan=p)
+        return f
+    t_seq32 = float(ctx["timer"].run([seq(mats32, X32, plans32, outs32)], ctx["fsteps"], 3)[:, 0].mean())
+    t_seq64 = float(ctx["timer"].run([seq(mats64, X64, plans64, outs64)], ctx["fsteps"], 3)[:, 0].mean())
+    same = all(torch.equal(a, b) for a, b in zip(outs32, B.Ys))
+    info = B.info()
+    return {"workload": "256 matrices (64 2D 5-pt, 64 3D 7-pt, 128 Zipf(2.2) mean 8-32), rows "
+                        "log-uniform [1e3, 2e5], FP32 values, k in {1, 4, 16}",
+            "matrices": len(specs), "total_nnz": int(sum(A.nnz for A in mats32)),
+            "total_rows": int(sum(A.m for A in mats32)), "tiles": info["tiles"], "grid": info["grid"],
+            "graph_us": t_graph * 1e6, "run_us": t_run * 1e6, "seq_f32_us": t_seq32 * 1e6,
+            "seq_f64_us": t_seq64 * 1e6, "gflops_graph": flops / t_graph / 1e9,
+            "eff_gbs_graph": bytes32 / t_graph / 1e9,
+            "speedup_vs_seq_f32": t_seq32 / t_graph, "speedup_vs_seq_f64": t_seq64 / t_graph,
+            "batched_equals_single_bitwise": bool(same), "gen_s": round(gen_s, 1),
+            "autotune_s": round(tune_s, 1)}
+
+
+# ---------------------------------------------------------------- headline (c1)
 
 def main():
     args = parse()
@@ -88,117 +344,52 @@ def main():
     dev = torch.device("cuda", 0)
     k = args.k
     t0 = time.time()
-    coo = spgen.workload_c1(seed=0, m=args.rows)
-    m, n = coo.m, coo.n
-    r = torch.from_numpy(coo.r).to(dev)
-    c = torch.from_numpy(coo.c).to(dev)
-    v = torch.from_numpy(coo.v).to(dev)
-    A = spx.from_coo(m, n, r, c, v)  # step a1 (device, one-time)
-    del r, c, v
-    nnz = A.nnz
-    plan_v = spx.Plan.for_matrix(A, spx.default_opts(1))  # step a2 (device, one-time)
+    A = upload(torch, spx, spgen.workload_c1(seed=0, m=args.rows), dev)  # step a1 (device)
+    m, n, nnz = A.m, A.n, A.nnz
+    plan_v = spx.Plan.for_matrix(A, spx.default_opts(1))  # step a2 (device)
     plan_m = spx.Plan.for_matrix(A, spx.default_opts(k))
     x = torch.from_numpy(spgen.uniform(n, 0, spgen.TAG_X)).to(dev)
     X = torch.from_numpy(spgen.uniform(n * k, 0, spgen.TAG_X + 1).reshape(n, k)).to(dev)
     y = torch.empty(m, dtype=torch.float64, device=dev)
     Y = torch.empty((m, k), dtype=torch.float64, device=dev)
-    flush = torch.zeros(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+    timer = Timer(torch, dev, not args.no_flush)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
 
-    def app_bytes(kk, sv=8, sx=8):
-        return (sv + 4) * nnz + sx * kk * n + sx * kk * m + 4 * (m + 1)
-
     flops_v, flops_m = 2 * nnz, 2 * nnz * k
-    bytes_v, bytes_m = app_bytes(1), app_bytes(k)
+    bytes_v, bytes_m = app_bytes(m, n, nnz), app_bytes(m, n, nnz, k)
+    step = [lambda: spx.spmv(A, x, y=y, plan=plan_v), lambda: spx.spmm(A, X, Y=Y, plan=plan_m)]
 
-    def run(steps, flush_each):
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
-        for s in range(steps):
-            if flush_each:
-                flush.add_(1.0)
-            e = ev[s]
-            e[0].record()
-            spx.spmv(A, x, y=y, plan=plan_v)
-            e[1].record()
-            spx.spmm(A, X, Y=Y, plan=plan_m)
-            e[2].record()
-        return ev
-
-    flush_each = not args.no_flush
-    run(args.warmup, flush_each)
+    timer.run(step, 0, args.warmup)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    ev = run(args.steps, flush_each)
-    torch.cuda.synchronize()
+    t = timer.run(step, args.steps, 0)
     wall = time.perf_counter() - w0
-    tv = np.array([e[0].elapsed_time(e[1]) for e in ev]) * 1e-3
-    tm = np.array([e[1].elapsed_time(e[2]) for e in ev]) * 1e-3
+    tv, tm = t[:, 0], t[:, 1]
     t_step = float(tv.mean() + tm.mean())
+    tw = Timer(torch, dev, False).run(step, 20, 2)
+    tvw, tmw = float(tw[:, 0].mean()), float(tw[:, 1].mean())
 
-    # secondary: warm (no flush) back-to-back
-    evw = run(20, False)
-    torch.cuda.synchronize()
-    tvw = float(np.mean([e[0].elapsed_time(e[1]) for e in evw])) * 1e-3
-    tmw = float(np.mean([e[1].elapsed_time(e[2]) for e in evw])) * 1e-3
+    def stats(ts, flops, b, warm):
+        return {"ms": ts.mean() * 1e3, "ms_median": float(np.median(ts)) * 1e3, "ms_min": float(ts.min()) * 1e3,
+                "gflops": flops / ts.mean() / 1e9, "eff_gbs": b / ts.mean() / 1e9,
+                "frac_hbm": b / ts.mean() / 1e9 / PEAK_HBM_GBS, "bytes": b, "warm_ms": warm * 1e3,
+                "warm_eff_gbs": b / warm / 1e9}
 
-    detail = {
-        "spmv": {"ms": tv.mean() * 1e3, "ms_median": float(np.median(tv)) * 1e3,
-                 "ms_min": float(tv.min()) * 1e3, "gflops": flops_v / tv.mean() / 1e9,
-                 "eff_gbs": bytes_v / tv.mean() / 1e9, "frac_hbm": bytes_v / tv.mean() / 1e9 / PEAK_HBM_GBS,
-                 "bytes": bytes_v, "warm_ms": tvw * 1e3, "warm_eff_gbs": bytes_v / tvw / 1e9},
-        "spmm": {"k": k, "ms": tm.mean() * 1e3, "ms_median": float(np.median(tm)) * 1e3,
-                 "ms_min": float(tm.min()) * 1e3, "gflops": flops_m / tm.mean() / 1e9,
-                 "eff_gbs": bytes_m / tm.mean() / 1e9, "frac_hbm": bytes_m / tm.mean() / 1e9 / PEAK_HBM_GBS,
-                 "bytes": bytes_m, "warm_ms": tmw * 1e3, "warm_eff_gbs": bytes_m / tmw / 1e9},
-        "plans": {"spmv": plan_v.info(), "spmm": plan_m.info()},
-        "flushed": flush_each, "setup_s": round(setup_s, 2), "wall_s_timed": round(wall, 4),
-        "source_hash": source_hash(),
-    }
-
-    if args.forms:
-        forms = {}
-        xf = x.float()
-        Xf = X.float()
-        for name, vals in (("f32", A.values.float()), ("bf16", A.values.to(torch.bfloat16))):
-            Aq = A.with_values(vals)
-            pv = spx.Plan.for_matrix(Aq, spx.default_opts(1, torch.float32))
-            pm = spx.Plan.for_matrix(Aq, spx.default_opts(k, torch.float32))
-            yq = torch.empty(m, dtype=torch.float32, device=dev)
-            Yq = torch.empty((m, k), dtype=torch.float32, device=dev)
-            tq = []
-            for s in range(args.warmup + args.steps):
-                if flush_each:
-                    flush.add_(1.0)
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-                e[0].record()
-                spx.spmv(Aq, xf, y=yq, plan=pv)
-                e[1].record()
-                spx.spmm(Aq, Xf, Y=Yq, plan=pm)
-                e[2].record()
-                tq.append(e)
-            torch.cuda.synchronize()
-            tq = tq[args.warmup:]
-            a = np.mean([e[0].elapsed_time(e[1]) for e in tq]) * 1e-3
-            b = np.mean([e[1].elapsed_time(e[2]) for e in tq]) * 1e-3
-            sv = 4 if name == "f32" else 2
-            forms[name] = {"spmv_ms": a * 1e3, "spmm_ms": b * 1e3,
-                           "spmv_eff_gbs": app_bytes(1, sv, 4) / a / 1e9,
-                           "spmm_eff_gbs": app_bytes(k, sv, 4) / b / 1e9,
-                           "speedup_spmv_vs_f64": float(tv.mean() / a),
-                           "speedup_spmm_vs_f64": float(tm.mean() / b)}
-        detail["forms"] = forms
+    detail = {"spmv": stats(tv, flops_v, bytes_v, tvw), "spmm": dict(stats(tm, flops_m, bytes_m, tmw), k=k),
+              "plans": {"spmv": plan_v.info(), "spmm": plan_m.info()}, "flushed": not args.no_flush,
+              "setup_s": round(setup_s, 2), "wall_s_timed_incl_flush": round(wall, 4),
+              "source_hash": source_hash()}
 
     cpu = None
     if not args.no_cpu:
         import oracle
-        ro = oracle.CSR(m, n, A.rowptr.cpu().numpy(), A.colind.cpu().numpy(), A.values.cpu().numpy())
-        xh = x.cpu().numpy()
-        Xh = X.cpu().numpy()
-        oracle.spmv(ro, xh)  # warm-up
+        ro = oracle_of(A)
+        xh, Xh = x.cpu().numpy(), X.cpu().numpy()
+        oracle.spmv(ro, xh)
         reps, spent, c0 = 0, 0.0, time.perf_counter()
-        tv_c, tm_c = 0.0, 0.0
-        while spent < args.cpu_seconds and reps < 50:
+        tv_c = tm_c = 0.0
+        while spent < args.cpu_seconds:
             a0 = time.perf_counter()
             oracle.spmv(ro, xh)
             a1 = time.perf_counter()
@@ -210,19 +401,40 @@ def main():
             spent = time.perf_counter() - c0
         cpu = {"value": (flops_v + flops_m) * reps / (tv_c + tm_c) / 1e9, "unit": "GFLOP/s",
                "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": f"full matrix, {reps} x (SpMV + SpMM k={k}) in FP64, OpenMP dynamic,64; "
-                         f"{spent:.1f} s; host caches not flushed",
+               "sample": f"the headline matrix, {reps} x (SpMV + SpMM k={k}), FP64, OpenMP "
+                         f"dynamic,64, {spent:.1f} s; host caches not flushed",
                "spmv_gflops": flops_v * reps / tv_c / 1e9, "spmm_gflops": flops_m * reps / tm_c / 1e9}
+        del ro
+
+    if not args.quick:
+        ctx = {"torch": torch, "spx": spx, "spgen": spgen, "dev": dev, "timer": timer,
+               "fsteps": args.form_steps, "tmp": os.environ.get("TMPDIR", "/tmp")}
+        forms = {}
+        for name in [f.strip() for f in args.forms.split(",") if f.strip()]:
+            f0 = time.time()
+            try:
+                if name == "c0":
+                    forms[name] = bench_c0(ctx)
+                elif name == "c2":
+                    forms[name] = bench_c2(ctx, A)
+                elif name == "c3":
+                    forms[name] = bench_c3(ctx)
+                elif name == "c4":
+                    forms[name] = bench_c4(ctx)
+                forms[name]["bench_s"] = round(time.time() - f0, 1)
+            except Exception as e:  # a failing form is reported, not hidden
+                forms[name] = {"error": repr(e)}
+            print(f"[bench] {name} done in {time.time() - f0:.1f} s", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        detail["forms"] = forms
 
     dom = "spmm" if tm.mean() >= tv.mean() else "spmv"
     t_dom = float(tm.mean() if dom == "spmm" else tv.mean())
     b_dom = bytes_m if dom == "spmm" else bytes_v
-    traffic = traffic_for(f"k_product_{dom}_c1", 1.0)
     roofline = {"bound": "hbm", "achieved": b_dom / t_dom / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": b_dom / t_dom / 1e9 / PEAK_HBM_GBS, "traffic": traffic,
+                "frac": b_dom / t_dom / 1e9 / PEAK_HBM_GBS, "traffic": traffic_for(f"k_product_{dom}_c1"),
                 "kernel": f"k_product ({'SpMM k=%d' % k if dom == 'spmm' else 'SpMV'}, FP64)",
                 "algorithmic_bytes_per_launch": b_dom}
-
     out = {
         "metric": METRIC,
         "value": (flops_v + flops_m) / t_step / 1e9,

@@ -61,12 +61,17 @@ typedef enum {
  * L satisfies upper[b-1] < L <= upper[b]; the last bin takes all longer
  * rows (its upper[] entry is ignored).  lanes[b] is the number of threads that
  * cooperate on one row of bin b: 1, 2, 4, 8, 16, 32, 64 (one wavefront) or
- * 256 (one workgroup); 0 marks a split bin (allowed only as the last bin):
- * each row is cut into segments of split_chunk nonzeros, one workgroup per
- * segment, and the segment partial sums are reduced in segment order. */
+ * 256 (one workgroup); SPX_LANES_STREAM makes a stream bin (SpMV: a
+ * workgroup loads the nonzeros of 256 consecutive bin rows as one flat,
+ * coalesced sequence and reduces each row from LDS; SpMM treats it as lanes
+ * = 1); 0 marks a split bin (allowed only as the last bin): each row is cut
+ * into segments of split_chunk nonzeros, one workgroup per segment, and the
+ * segment partial sums are reduced in segment order. */
+#define SPX_LANES_STREAM 512
 #define SPX_FLAG_NO_NT_STORE 1u  /* plain (temporal) stores for y / Y */
 #define SPX_FLAG_SCALAR_X 2u     /* SpMM: one element per lane, no vector loads of X */
 #define SPX_FLAG_NO_XCD_MAP 4u   /* keep hardware workgroup order (no per-XCD contiguous tiles) */
+#define SPX_FLAG_ONE_ROW 8u      /* one row per row group (no multi-row groups for short rows) */
 typedef struct spx_plan_opts {
   int32_t nbins;
   int32_t upper[SPX_MAX_BINS];
@@ -212,6 +217,16 @@ spx_status csr_batch_run(const spx_batch *batch, void *stream);
 /* Tiles, workgroups of the persistent launch, and total split segments. */
 spx_status csr_batch_info(const spx_batch *batch, int64_t *ntiles, int32_t *grid, int64_t *nsegments);
 void csr_batch_destroy(spx_batch *batch);
+
+/* ---------------------------------------------------------------- probes
+ * Memory-system probes (the GPU counterparts of the paper's read / write
+ * bandwidth microbenchmarks, Sec. 2.1 and 2.2), used to calibrate measured
+ * bandwidth.  kind 0: streaming read of buf (buf2: optional device double
+ * that keeps the loads live); 1: write buf; 2: non-temporal write of buf;
+ * 3: non-temporal copy buf -> buf2; 4: read-modify-write of buf (a cache
+ * flush).  bytes is rounded down to 16-byte units; buffers must be 16-byte
+ * aligned; blocks <= 0 picks 4096 workgroups of 256 threads. */
+spx_status spx_probe(int32_t kind, void *buf, void *buf2, size_t bytes, int32_t blocks, void *stream);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,6 @@ the GPU; there is no CPU path, and importing an operation without the built
 library raises.
 """
 from ._lib import PlanOpts, SpxError, missing_symbols  # noqa: F401
-from .ops import (CSR, CSCIndex, Plan, default_opts, from_coo, sddmm, spmm, spmv,  # noqa: F401
+from .ops import (CSR, CSCIndex, Plan, default_opts, from_coo, probe, sddmm, spmm, spmv,  # noqa: F401
                   spmv_t, transpose_index, validate, version)
 from .autograd import GradContext, SpMVFunction, spmv_autograd  # noqa: F401

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libspx.so")
+# SPX_LIB may point at another build of the same library (for comparisons)
+LIB_PATH = os.environ.get("SPX_LIB") or os.path.join(_PKG, "libspx.so")
 
 SPX_OK, SPX_ERR_INVALID, SPX_ERR_UNSUPPORTED, SPX_ERR_WORKSPACE, SPX_ERR_HIP = range(5)
 SPX_F64, SPX_F32, SPX_BF16 = 0, 1, 2
@@ -17,6 +18,7 @@ SPX_MAX_BINS = 12
 SPX_FLAG_NO_NT_STORE = 1
 SPX_FLAG_SCALAR_X = 2
 SPX_FLAG_NO_XCD_MAP = 4
+SPX_FLAG_ONE_ROW = 8
 
 STATUS_NAMES = {0: "SPX_OK", 1: "SPX_ERR_INVALID", 2: "SPX_ERR_UNSUPPORTED",
                 3: "SPX_ERR_WORKSPACE", 4: "SPX_ERR_HIP"}
@@ -98,6 +100,7 @@ SIGNATURES = {
     "csr_batch_run": (ctypes.c_int, [P, P]),
     "csr_batch_info": (ctypes.c_int, [P, P, P, P]),
     "csr_batch_destroy": (None, [P]),
+    "spx_probe": (ctypes.c_int, [i32, P, P, ctypes.c_size_t, i32, P]),
 }
 
 _lib = None

@@ -18,6 +18,8 @@ import torch
 from ._lib import PlanOpts
 from .ops import CSR, Plan, default_opts, spmm, spmv
 
+STREAM = 512  # SPX_LANES_STREAM
+
 
 def structure_key(A: CSR, k: int) -> str:
     h = hashlib.sha1()
@@ -42,7 +44,7 @@ def candidates(k: int, vdtype=torch.float64) -> list:
     dbl = _copy(base)
     for b in range(base.nbins):
         l = base.lanes[b]
-        if l:
+        if l and l != STREAM:
             half.lanes[b] = max(1, l // 2) if l != 256 else 64
             dbl.lanes[b] = min(64, l * 2) if l < 64 else 256
     out += [half, dbl]
@@ -54,7 +56,14 @@ def candidates(k: int, vdtype=torch.float64) -> list:
         nosplit = _copy(base)
         nosplit.lanes[base.nbins - 1] = 256
         out.append(nosplit)
-    coarse = PlanOpts.from_dict({"nbins": 3, "upper": [8, 256], "lanes": [1 if k > 1 else 4, 64, 0],
+    if k == 1:
+        # row groups of 1..32 lanes for the short rows instead of a stream bin
+        sub = PlanOpts.from_dict({"nbins": 9, "upper": [1, 2, 4, 8, 16, 32, 128, 2048],
+                                  "lanes": [1, 2, 4, 8, 16, 32, 64, 256, 0],
+                                  "split_chunk": base.split_chunk, "kahan_len": base.kahan_len,
+                                  "max_k": k, "flags": 0})
+        out.append(sub)
+    coarse = PlanOpts.from_dict({"nbins": 3, "upper": [8, 256], "lanes": [1 if k > 1 else STREAM, 64, 0],
                                  "split_chunk": base.split_chunk, "kahan_len": base.kahan_len,
                                  "max_k": k, "flags": 0})
     out.append(coarse)

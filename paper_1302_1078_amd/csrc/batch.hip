@@ -76,6 +76,10 @@ __device__ __forceinline__ void run_tile(const ProdArgs& a, const BinDesc& d, in
       if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 32, 4>(a, d, tile);
       else do_rows<C, 32, 1>(a, d, tile);
       break;
+    case SPX_LANES_STREAM:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_stream<C>(a, d, tile);
+      else do_rows<C, 1, 1>(a, d, tile);
+      break;
     default: do_split<C>(a, d, tile); break;
   }
 }
@@ -293,7 +297,7 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
         per_tile = o.split_chunk;
       } else {
         const int gg = bd.lanes > kl ? bd.lanes : kl;
-        const int rpb = kWG / gg;
+        const int rpb = (bd.lanes == SPX_LANES_STREAM) ? kWG : (kWG / gg) * bd.rpg;
         double len;
         if (bd.bin < o.nbins - 1) len = o.upper[bd.bin];
         else len = (o.nbins >= 2) ? 2.0 * o.upper[o.nbins - 2] : static_cast<double>(d.nnz) / (d.m > 0 ? d.m : 1);

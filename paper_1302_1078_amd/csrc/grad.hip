@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
   }
   // row groups of G lanes; a bin may give each group several rows (rpg),
   // taken in the same order as the product kernels
-  const int G = d.lanes;
+  const int G = (d.lanes == SPX_LANES_STREAM) ? 1 : d.lanes;  // stream bins: a row per thread
   const int ng = kWG / G;
   for (int j = 0; j < d.rpg; ++j) {
     const int idx = (tile * d.rpg + j) * ng + t / G;

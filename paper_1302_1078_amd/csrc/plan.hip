@@ -197,7 +197,8 @@ spx_status check_opts(const spx_plan_opts* o) {
 }  // namespace
 
 int lanes_valid(int l) {
-  return l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64 || l == 256;
+  return l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64 || l == 256 ||
+         l == SPX_LANES_STREAM;
 }
 
 }  // namespace spx
@@ -212,11 +213,12 @@ extern "C" spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan
   o->max_k = k;
   o->flags = 0;
   if (k == 1) {
-    // SpMV: lanes per row grow with row length; long rows split.
-    const int32_t upper[] = {1, 2, 4, 8, 16, 32, 128, 2048, 0};
-    const int32_t lanes[] = {1, 2, 4, 8, 16, 32, 64, 256, 0};
-    o->nbins = 9;
-    for (int b = 0; b < 9; ++b) {
+    // SpMV: short rows streamed per workgroup, then a wavefront, a workgroup
+    // per row, and split segments for the longest rows.
+    const int32_t upper[] = {32, 128, 2048, 0};
+    const int32_t lanes[] = {SPX_LANES_STREAM, 64, 256, 0};
+    o->nbins = 4;
+    for (int b = 0; b < 4; ++b) {
       o->upper[b] = upper[b];
       o->lanes[b] = lanes[b];
     }
@@ -230,7 +232,7 @@ extern "C" spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan
       o->upper[b] = upper[b];
       o->lanes[b] = lanes[b];
     }
-    o->split_chunk = 512;
+    o->split_chunk = 4096;
   }
   return SPX_OK;
 }
@@ -368,18 +370,22 @@ void bins_from_plan(const spx_plan* p, ProdArgs& a, int kl) {
   const bool pad = !(o.flags & SPX_FLAG_NO_XCD_MAP);
   for (int b = o.nbins - 1; b >= 0; --b) {  // long-row bins first
     const int32_t rows = p->bin_off[b + 1] - p->bin_off[b];
-    const int32_t lanes = o.lanes[b];
+    int32_t lanes = o.lanes[b];
+    const bool stream = (lanes == SPX_LANES_STREAM);
+    if (stream && !(kl == 1 && a.k == 1)) lanes = 1;  // SpMM: row groups of KL lanes
     const int32_t units = (lanes == 0) ? p->nseg : rows;
     if (units == 0) continue;
     // short-row bins (every row fits one nonzero per slot) serve 4 rows per
     // group to raise the number of independent loads in flight
     int32_t rpg = 1;
-    if (kl == 1 && a.k == 1 && lanes != 0 && lanes <= 32 && b < o.nbins - 1) {
+    if (kl == 1 && a.k == 1 && !(o.flags & SPX_FLAG_ONE_ROW) && lanes != 0 && lanes <= 32 &&
+        b < o.nbins - 1) {
       const int32_t slots = lanes >= kl ? lanes / kl : 1;
       if (o.upper[b] <= slots) rpg = 4;
     }
     int32_t rpb = 1;
-    if (lanes != 0) rpb = (kWG / (lanes > kl ? lanes : kl)) * rpg;
+    if (lanes == SPX_LANES_STREAM) rpb = kWG;  // one row per thread
+    else if (lanes != 0) rpb = (kWG / (lanes > kl ? lanes : kl)) * rpg;
     if (rpb < 1) rpb = 1;
     int32_t nblk = (units + rpb - 1) / rpb;
     if (pad) nblk = (nblk + 7) / 8 * 8;

@@ -33,7 +33,10 @@ namespace {
 
 using namespace prod;
 
-template <class C>
+// MR: instantiate the multi-row path of short-row bins.  It costs VGPRs in
+// the whole fused kernel, so launches whose bins do not use it run the MR =
+// false variant (higher occupancy).
+template <class C, bool MR>
 __global__ __launch_bounds__(kWG) void k_product(const ProdArgs a) {
   const int b = blockIdx.x;
   int bi = 0;
@@ -51,28 +54,32 @@ __global__ __launch_bounds__(kWG) void k_product(const ProdArgs a) {
     case 64: do_rows<C, 64, 1>(a, d, tile); break;
     case 256: do_rows<C, 256, 1>(a, d, tile); break;
     case 1001:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 1, 4>(a, d, tile);
+      if constexpr (MR && C::KL == 1 && C::VEC == 1) do_rows<C, 1, 4>(a, d, tile);
       else do_rows<C, 1, 1>(a, d, tile);
       break;
     case 1002:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 2, 4>(a, d, tile);
+      if constexpr (MR && C::KL == 1 && C::VEC == 1) do_rows<C, 2, 4>(a, d, tile);
       else do_rows<C, 2, 1>(a, d, tile);
       break;
     case 1004:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 4, 4>(a, d, tile);
+      if constexpr (MR && C::KL == 1 && C::VEC == 1) do_rows<C, 4, 4>(a, d, tile);
       else do_rows<C, 4, 1>(a, d, tile);
       break;
     case 1008:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 8, 4>(a, d, tile);
+      if constexpr (MR && C::KL == 1 && C::VEC == 1) do_rows<C, 8, 4>(a, d, tile);
       else do_rows<C, 8, 1>(a, d, tile);
       break;
     case 1016:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 16, 4>(a, d, tile);
+      if constexpr (MR && C::KL == 1 && C::VEC == 1) do_rows<C, 16, 4>(a, d, tile);
       else do_rows<C, 16, 1>(a, d, tile);
       break;
     case 1032:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 32, 4>(a, d, tile);
+      if constexpr (MR && C::KL == 1 && C::VEC == 1) do_rows<C, 32, 4>(a, d, tile);
       else do_rows<C, 32, 1>(a, d, tile);
+      break;
+    case SPX_LANES_STREAM:
+      if constexpr (C::KL == 1 && C::VEC == 1) do_stream<C>(a, d, tile);
+      else do_rows<C, 1, 1>(a, d, tile);
       break;
     default: do_split<C>(a, d, tile); break;
   }
@@ -80,9 +87,14 @@ __global__ __launch_bounds__(kWG) void k_product(const ProdArgs a) {
 
 template <typename VT, typename XT, int VECMAX>
 spx_status launch_vt(ProdArgs& a, int kl, int vec, unsigned grid, hipStream_t st) {
+  bool mr = false;
+  for (int i = 0; i < a.nbins; ++i) mr = mr || (a.bins[i].rpg > 1);
 #define SPX_CASE(KL_, VEC_)                                                         \
   if (kl == KL_ && vec == VEC_) {                                                   \
-    k_product<Cfg<VT, XT, KL_, VEC_>><<<grid, kWG, 0, st>>>(a);                     \
+    if (KL_ == 1 && VEC_ == 1 && mr)                                                \
+      k_product<Cfg<VT, XT, KL_, VEC_>, true><<<grid, kWG, 0, st>>>(a);             \
+    else                                                                            \
+      k_product<Cfg<VT, XT, KL_, VEC_>, false><<<grid, kWG, 0, st>>>(a);            \
     SPX_LAUNCHED("k_product");                                                      \
     return SPX_OK;                                                                  \
   }

@@ -318,6 +318,134 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
   }
 }
 
+// Stream bin (SpMV only): one workgroup takes kStreamRows consecutive rows of
+// the bin and treats their nonzeros as one flat sequence.  Lanes load that
+// sequence in chunks of kStreamChunk with consecutive lanes on consecutive
+// nonzeros (coalesced, kStreamChunk / 256 independent loads per lane), gather
+// x, and park the products in LDS; then every thread sums its own row's
+// products in ascending order.  A chunk costs two dependent global trips for
+// up to 2,048 nonzeros, where a row group pays a trip chain per row.
+constexpr int kStreamRows = 256;
+constexpr int kStreamChunk = 1024;
+constexpr int kStreamPer = kStreamChunk / kWG;
+
+template <class C>
+__device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, int tile) {
+  static_assert(C::KL == 1 && C::VEC == 1, "stream bins serve SpMV only");
+  using XT = typename C::XT;
+  using AT = typename C::AT;
+  __shared__ int32_t s_off[kStreamRows + 1];
+  __shared__ int32_t s_p0[kStreamRows];
+  __shared__ AT s_prod[kStreamChunk];
+  __shared__ int32_t s_wsum[kWG / kWave];
+  if (tile * kStreamRows >= d.nrows) return;
+  const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+  const int idx = tile * kStreamRows + t;
+  const bool active = idx < d.nrows;
+  int32_t row = 0, p0 = 0, p1 = 0;
+  if (active) row_range(a, d, idx, row, p0, p1);
+  const int32_t L = p1 - p0;
+  // exclusive prefix of the row lengths over the workgroup
+  int32_t inc = L;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t u = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += u;
+  }
+  if (lane == kWave - 1) s_wsum[w] = inc;
+  __syncthreads();
+  int32_t before = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < kWG / kWave; ++i) {
+    if (i < w) before += s_wsum[i];
+    total += s_wsum[i];
+  }
+  const int32_t off = before + inc - L;
+  s_off[t] = off;
+  s_p0[t] = p0;
+  if (t == kWG - 1) s_off[kStreamRows] = total;
+  total = __builtin_amdgcn_readfirstlane(total);
+  __syncthreads();
+
+  const XT* X = static_cast<const XT*>(a.X);
+  const bool comp = C::kComp && (L > a.kahan_len);
+  AT acc = AT(0);
+  // Loads of one chunk: the row of each element is the last r with
+  // s_off[r] <= j, found by a fixed 8-step branchless search run for all
+  // kStreamPer elements in lockstep (the LDS reads of a step are independent,
+  // so a lane waits for 8 LDS round trips per chunk, not 8 per element).
+  auto fetch = [&](int32_t base, int32_t (&cc)[kStreamPer], XT (&vv)[kStreamPer]) {
+    int32_t jj[kStreamPer], lo[kStreamPer];
+#pragma unroll
+    for (int u = 0; u < kStreamPer; ++u) {
+      jj[u] = base + u * kWG + t;
+      lo[u] = 0;
+    }
+#pragma unroll
+    for (int step = kStreamRows / 2; step >= 1; step >>= 1) {
+#pragma unroll
+      for (int u = 0; u < kStreamPer; ++u)
+        if (s_off[lo[u] + step] <= jj[u]) lo[u] += step;
+    }
+#pragma unroll
+    for (int u = 0; u < kStreamPer; ++u) {
+      const int32_t p = s_p0[lo[u]] + (jj[u] - s_off[lo[u]]);
+      const bool h = jj[u] < total;
+      cc[u] = h ? ld_stream(a.colind + p) : 0;
+      vv[u] = h ? value_at<C>(a, p) : XT(0);
+    }
+  };
+  // software pipeline: the next chunk's colind / values are in flight while
+  // the current chunk gathers x and reduces through LDS
+  int32_t cA[kStreamPer];
+  XT vA[kStreamPer];
+  fetch(0, cA, vA);
+  for (int32_t base = 0; base < total; base += kStreamChunk) {
+    const bool more = base + kStreamChunk < total;
+    int32_t cB[kStreamPer];
+    XT vB[kStreamPer];
+    if (more) fetch(base + kStreamChunk, cB, vB);
+    XT xv[kStreamPer];
+#pragma unroll
+    for (int u = 0; u < kStreamPer; ++u)
+      xv[u] = (base + u * kWG + t < total) ? X[static_cast<int64_t>(cA[u]) * a.ldx] : XT(0);
+#pragma unroll
+    for (int u = 0; u < kStreamPer; ++u) s_prod[u * kWG + t] = vA[u] * xv[u];
+    __syncthreads();
+    const int32_t b0 = max(off, base) - base;
+    const int32_t b1 = min(off + L, base + kStreamChunk) - base;
+#pragma unroll 8
+    for (int32_t i = b0; i < b1; ++i) acc += s_prod[i];
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < kStreamPer; ++u) {
+        cA[u] = cB[u];
+        vA[u] = vB[u];
+      }
+    }
+  }
+  if (!active) return;
+  XT out[1];
+  if constexpr (C::kComp) {
+    if (comp) {
+      // rows above kahan_len (not placed in stream bins by the planner):
+      // compensated sum of the row straight from memory
+      Comp cc;
+      cc.init();
+      for (int32_t p = p0; p < p1; ++p)
+        cc.add_prod(value_at<C>(a, p), X[static_cast<int64_t>(ld_stream(a.colind + p)) * a.ldx]);
+      out[0] = static_cast<XT>(cc.value());
+    } else {
+      out[0] = acc;
+    }
+  } else {
+    out[0] = acc;
+  }
+  store_y<XT, 1>(static_cast<XT*>(a.Y) + static_cast<int64_t>(row) * a.ldy, out,
+                 !(a.flags & SPX_FLAG_NO_NT_STORE));
+}
+
 // One workgroup per segment of a split row; the last arrival reduces.
 template <class C>
 __device__ __forceinline__ void do_split(const ProdArgs& a, const BinDesc& d, int tile) {

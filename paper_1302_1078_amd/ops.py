@@ -285,3 +285,15 @@ def sddmm(A: CSR, dY: torch.Tensor, X: torch.Tensor, plan: Plan | None = None,
                       1 if vec else dY.stride(0), _ptr(X), 1 if vec else X.stride(0), _ptr(out),
                       dtype_code(dY), _plan_ptr(plan), _stream()), "csr_sddmm")
     return out
+
+
+# ---------------------------------------------------------------- probes
+
+PROBE_KINDS = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "flush": 4}
+
+
+def probe(kind: str, buf: torch.Tensor, buf2: torch.Tensor | None = None, blocks: int = 0) -> None:
+    """Launch one memory probe over buf (see spx_probe in include/spx.h)."""
+    _dev(buf, buf2)
+    check(_lib.load().spx_probe(PROBE_KINDS[kind], _ptr(buf), _ptr(buf2), buf.numel() * buf.element_size(),
+                                blocks, _stream()), "spx_probe")

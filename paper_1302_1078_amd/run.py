@@ -1,0 +1,78 @@
+"""Run one product on one synthetic workload a few times (for profilers).
+
+    python -m paper_1302_1078_amd.run --workload c1 --op spmm --k 16 --reps 5
+
+Workloads (seed 0): c1 power-law 1,048,576 square (Zipf 2.0, mean 16, max
+20,000, hot columns); stencil27 (27-point stencil on 128^3); c3 power-law
+524,288 (mean 20); c0 uniform 10,000 x 10,000.  --probe-copy-mib N first
+runs a non-temporal copy of N MiB (a known-size kernel that calibrates the
+profiler's traffic counters).  Each product call is preceded by a cache flush
+unless --no-flush.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c3", "stencil27"])
+    ap.add_argument("--op", default="spmv", choices=["spmv", "spmm"])
+    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--lanes", default="", help="comma list: single-bin plans to run after the default")
+    ap.add_argument("--probe-copy-mib", type=int, default=0)
+    ap.add_argument("--no-flush", action="store_true")
+    args = ap.parse_args(argv)
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import torch
+
+    import spgen
+    from . import ops
+    from ._lib import PlanOpts
+
+    dev = torch.device("cuda", 0)
+    if args.probe_copy_mib:
+        a = torch.zeros(args.probe_copy_mib << 17, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        ops.probe("copy", a, b)
+        torch.cuda.synchronize()
+        del a, b
+    coo = {"c0": lambda: spgen.workload_c0(0), "c1": lambda: spgen.workload_c1(0),
+           "c3": lambda: spgen.workload_c3(0), "stencil27": lambda: spgen.workload_c2_stencil(0)}[args.workload]()
+    A = ops.from_coo(coo.m, coo.n, torch.from_numpy(coo.r).to(dev), torch.from_numpy(coo.c).to(dev),
+                     torch.from_numpy(coo.v).to(dev))
+    vt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[args.dtype]
+    xt = torch.float64 if args.dtype == "f64" else torch.float32
+    A = A.with_values(A.values.to(vt))
+    k = 1 if args.op == "spmv" else args.k
+    X = torch.from_numpy(spgen.uniform(A.n * k, 0)).to(dev).to(xt)
+    X = X if k > 1 else X.reshape(-1)
+    X = X.reshape(A.n, k) if k > 1 else X
+    Y = torch.empty((A.m, k) if k > 1 else (A.m,), dtype=xt, device=dev)
+    flush = None if args.no_flush else torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+    plans = [ops.Plan.for_matrix(A, ops.default_opts(k, vt))]
+    for l in [int(s) for s in args.lanes.split(",") if s.strip()]:
+        plans.append(ops.Plan.for_matrix(A, PlanOpts.from_dict({"nbins": 1, "upper": [], "lanes": [l],
+                                                                 "split_chunk": 4096, "max_k": k})))
+    for plan in plans:
+        for _ in range(args.reps):
+            if flush is not None:
+                ops.probe("flush", flush)
+            if k == 1:
+                ops.spmv(A, X, y=Y, plan=plan)
+            else:
+                ops.spmm(A, X, Y=Y, plan=plan)
+    torch.cuda.synchronize()
+    print(f"ran {args.op} on {args.workload} ({A.m} rows, {A.nnz} nnz, k={k}, {args.dtype}) "
+          f"x{args.reps} per plan, {len(plans)} plan(s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -37,8 +37,13 @@ def plan_variants(spx, A, k=1):
     """(name, plan) pairs: none, default, and one plan per lane width."""
     G = to_gpu(A)
     out = [("none", None), ("default", spx.Plan.for_matrix(G, spx.default_opts(k)))]
-    for lanes in (1, 2, 4, 8, 16, 32, 64, 256):
+    for lanes in (1, 2, 4, 8, 16, 32, 64, 256, 512):
         out.append((f"lanes{lanes}", spx.Plan.for_matrix(G, single_bin_opts(lanes, k))))
+    out.append(("sub-bins", spx.Plan.for_matrix(G, spx.PlanOpts.from_dict(
+        {"nbins": 7, "upper": [1, 2, 4, 8, 16, 32], "lanes": [1, 2, 4, 8, 16, 32, 256],
+         "max_k": k}))))
+    out.append(("stream+split", spx.Plan.for_matrix(G, spx.PlanOpts.from_dict(
+        {"nbins": 2, "upper": [40], "lanes": [512, 0], "split_chunk": 256, "max_k": k}))))
     out.append(("split", spx.Plan.for_matrix(G, single_bin_opts(0, k, chunk=256))))
     out.append(("lanes8+split", spx.Plan.for_matrix(G, two_bin_opts(300, 8, k, chunk=256))))
     return G, out
