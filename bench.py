@@ -289,7 +289,8 @@ def bench_c4(ctx):
         bytes32 += app_bytes(A.m, A.n, A.nnz, s.k, 4, 4)
         bytes64 += app_bytes(A.m, A.n, A.nnz, s.k, 8, 8)
     gen_s = time.time() - t0
-    cache = os.path.join(ctx["tmp"], "autotune_c4.json")
+    import tempfile
+    cache = os.path.join(tempfile.mkdtemp(prefix="spx_tune_"), "autotune_c4.json")  # tune afresh
     t1 = time.time()
     opts = [autotune.tune(A, X, reps=3, cache_path=cache)[0] for A, X in zip(mats32, X32)]
     tune_s = time.time() - t1

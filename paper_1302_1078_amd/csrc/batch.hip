@@ -93,16 +93,27 @@ __global__ void k_batch_reset(int32_t* head) { *head = 0; }
 // back edge, sending lane 0 and the other lanes to different loop headers;
 // under exec masking the other lanes would then re-read the same tile id
 // forever.
+// Tiles are popped in runs of kPop (one atomic per run): with hundreds of
+// thousands of small tiles a single queue head would otherwise serialise
+// the launch on one address.
+constexpr int kPop = 16;
+
 template <typename VT, typename XT, int V>
 __global__ __launch_bounds__(kWG) void k_batch(const BatchArgs b) {
   __shared__ int32_t next;
+  int32_t id = 0, end = 0;
   for (;;) {
     __syncthreads();  // LDS of the previous tile is no longer in use
-    if (threadIdx.x == 0) next = atomicAdd(b.head, 1);
-    __syncthreads();
-    const int32_t id = __builtin_amdgcn_readfirstlane(next);
+    if (id >= end) {  // uniform: id and end are wave-uniform SGPR values
+      if (threadIdx.x == 0) next = atomicAdd(b.head, kPop);
+      __syncthreads();
+      id = __builtin_amdgcn_readfirstlane(next);
+      end = min(id + kPop, b.ntiles);
+      __syncthreads();
+    }
     if (id >= b.ntiles) break;
     const TileDesc* tp = b.tiles + id;
+    ++id;
     const int32_t mat = __builtin_amdgcn_readfirstlane(tp->mat);
     const int32_t slot = __builtin_amdgcn_readfirstlane(tp->slot);
     const int32_t layout = __builtin_amdgcn_readfirstlane(tp->layout);

@@ -26,6 +26,8 @@ def main(argv=None):
     ap.add_argument("--lanes", default="", help="comma list: single-bin plans to run after the default")
     ap.add_argument("--probe-copy-mib", type=int, default=0)
     ap.add_argument("--no-flush", action="store_true")
+    ap.add_argument("--bandwidth", action="store_true",
+                    help="only time the memory probes (read / write / copy of 1 GiB) and exit")
     args = ap.parse_args(argv)
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -38,6 +40,9 @@ def main(argv=None):
     from ._lib import PlanOpts
 
     dev = torch.device("cuda", 0)
+    if args.bandwidth:
+        bandwidth(torch, ops, dev)
+        return
     if args.probe_copy_mib:
         a = torch.zeros(args.probe_copy_mib << 17, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -72,6 +77,31 @@ def main(argv=None):
     torch.cuda.synchronize()
     print(f"ran {args.op} on {args.workload} ({A.m} rows, {A.nnz} nnz, k={k}, {args.dtype}) "
           f"x{args.reps} per plan, {len(plans)} plan(s)", flush=True)
+
+
+def bandwidth(torch, ops, dev, reps: int = 20):
+    """Median GB/s of the streaming probes over 1 GiB buffers (HIP events)."""
+    import statistics
+    a = torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.zeros_like(a)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    nbytes = a.numel() * 8
+    cases = {"read": (lambda: ops.probe("read", a, sink, 16384), nbytes),
+             "write": (lambda: ops.probe("write", a, None, 16384), nbytes),
+             "write_nt": (lambda: ops.probe("write_nt", a, None, 16384), nbytes),
+             "copy": (lambda: ops.probe("copy", a, b, 16384), 2 * nbytes)}
+    for name, (fn, moved) in cases.items():
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            ts.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = statistics.median(x.elapsed_time(y) for x, y in ts)
+        print(f"{name:9s} {moved / 2**30:.0f} GiB moved  {ms * 1e3:8.1f} us  {moved / ms / 1e6:7.0f} GB/s", flush=True)
 
 
 if __name__ == "__main__":
