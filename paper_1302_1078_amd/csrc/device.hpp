@@ -17,11 +17,18 @@ constexpr int kWave = 64;  // CDNA wavefront width
 
 // ------------------------------------------------------------------ loads / stores
 
-// Streaming (non-temporal) loads for data read exactly once (colind, values):
-// they should not evict the gathered x / X lines from L2.
+// Loads of the matrix stream (colind, values).  With NT they are
+// non-temporal, so a stream read once does not evict gathered x lines from
+// L2; a kernel that comes back to a line (the lanes of an SpMM row group
+// walk a row over several rounds) loads it normally.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_mat(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p) {
-  return __builtin_nontemporal_load(p);
+  return ld_mat<true>(p);
 }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
@@ -33,16 +40,19 @@ template <typename VT>
 struct ValueLoad;
 template <>
 struct ValueLoad<double> {
-  static __device__ __forceinline__ double get(const double* p) { return ld_stream(p); }
+  template <bool NT = true>
+  static __device__ __forceinline__ double get(const double* p) { return ld_mat<NT>(p); }
 };
 template <>
 struct ValueLoad<float> {
-  static __device__ __forceinline__ float get(const float* p) { return ld_stream(p); }
+  template <bool NT = true>
+  static __device__ __forceinline__ float get(const float* p) { return ld_mat<NT>(p); }
 };
 template <>
 struct ValueLoad<uint16_t> {
+  template <bool NT = true>
   static __device__ __forceinline__ float get(const uint16_t* p) {
-    return bf16_to_f32(ld_stream(p));
+    return bf16_to_f32(ld_mat<NT>(p));
   }
 };
 

@@ -11,7 +11,12 @@
 namespace spx {
 namespace prod {
 
-constexpr int kUnroll = 4;
+// Independent nonzeros per lane and round.  SPX_UNROLL overrides it at build
+// time (for unroll-depth sweeps).
+#ifndef SPX_UNROLL
+#define SPX_UNROLL 4
+#endif
+constexpr int kUnroll = SPX_UNROLL;
 
 template <typename VT_, typename XT_, int KL_, int VEC_>
 struct Cfg {
@@ -21,6 +26,9 @@ struct Cfg {
   static constexpr int KL = KL_;
   static constexpr int VEC = VEC_;
   static constexpr bool kComp = std::is_same<XT_, float>::value;
+  // SpMV streams colind / values non-temporally; SpMM row groups revisit
+  // their lines (see ld_mat)
+  static constexpr bool kNT = (KL_ * VEC_ == 1);
 };
 
 template <typename T, int N>
@@ -56,71 +64,58 @@ __device__ __forceinline__ void store_y(T* p, const T (&in)[N], bool nt) {
 
 template <class C>
 __device__ __forceinline__ typename C::XT value_at(const ProdArgs& a, int32_t p) {
-  const int32_t q = a.vperm ? ld_stream(a.vperm + p) : p;
+  const int32_t q = a.vperm ? ld_mat<C::kNT>(a.vperm + p) : p;
   return static_cast<typename C::XT>(
-      ValueLoad<typename C::VT>::get(static_cast<const typename C::VT*>(a.values) + q));
+      ValueLoad<typename C::VT>::template get<C::kNT>(static_cast<const typename C::VT*>(a.values) + q));
 }
 
 // Accumulate the nonzeros p = p0 + slot, p0 + slot + S, ... < p1 of one row
 // into acc (plain) or cacc (compensated) for the VEC columns at `col`.
+// Every round issues the loads of kUnroll nonzeros before using any; the
+// last round is masked rather than finished one nonzero at a time, so a slot
+// with n nonzeros waits for ceil(n / kUnroll) gather round trips.  Products
+// are added in ascending p either way.
 template <class C, int S>
 __device__ __forceinline__ void accumulate(const ProdArgs& a, int32_t p0, int32_t p1, int slot,
                                            int col, bool comp, typename C::AT (&acc)[C::VEC],
                                            Comp (&cacc)[C::VEC]) {
   using XT = typename C::XT;
   constexpr int VEC = C::VEC;
+  constexpr int U = kUnroll;
   const XT* X = static_cast<const XT*>(a.X) + col;
   const int64_t ldx = a.ldx;
-  int32_t p = p0 + slot;
-  if (!C::kComp || !comp) {
-    for (; p + (kUnroll - 1) * S < p1; p += kUnroll * S) {
-      int32_t c[kUnroll];
-      XT v[kUnroll];
-      XT xv[kUnroll][VEC];
+  for (int32_t p = p0 + slot; p < p1; p += U * S) {
+    bool h[U];
+    int32_t c[U];
+    XT v[U];
+    XT xv[U][VEC];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        c[u] = ld_stream(a.colind + p + u * S);
-        v[u] = value_at<C>(a, p + u * S);
+    for (int u = 0; u < U; ++u) {
+      h[u] = p + u * S < p1;
+      c[u] = h[u] ? ld_mat<C::kNT>(a.colind + p + u * S) : 0;
+      v[u] = h[u] ? value_at<C>(a, p + u * S) : XT(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (h[u]) {
+        load_x<XT, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xv[u][e] = XT(0);
       }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) load_x<XT, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[e] = fma_t(v[u], xv[u][e], acc[e]);
     }
-    for (; p < p1; p += S) {
-      const int32_t c = ld_stream(a.colind + p);
-      const XT v = value_at<C>(a, p);
-      XT xv[VEC];
-      load_x<XT, VEC>(X + static_cast<int64_t>(c) * ldx, xv);
+    if (!C::kComp || !comp) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[e] = fma_t(v, xv[e], acc[e]);
-    }
-  } else if constexpr (C::kComp) {
-    for (; p + (kUnroll - 1) * S < p1; p += kUnroll * S) {
-      int32_t c[kUnroll];
-      float v[kUnroll];
-      float xv[kUnroll][VEC];
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        c[u] = ld_stream(a.colind + p + u * S);
-        v[u] = value_at<C>(a, p + u * S);
-      }
+        for (int e = 0; e < VEC; ++e)
+          if (h[u]) acc[e] = fma_t(v[u], xv[u][e], acc[e]);
+    } else if constexpr (C::kComp) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) load_x<float, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) cacc[e].add_prod(v[u], xv[u][e]);
-    }
-    for (; p < p1; p += S) {
-      const int32_t c = ld_stream(a.colind + p);
-      const float v = value_at<C>(a, p);
-      float xv[VEC];
-      load_x<float, VEC>(X + static_cast<int64_t>(c) * ldx, xv);
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) cacc[e].add_prod(v, xv[e]);
+        for (int e = 0; e < VEC; ++e)
+          if (h[u]) cacc[e].add_prod(v[u], xv[u][e]);
     }
   }
 }
@@ -213,7 +208,7 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
       for (int j = 0; j < R; ++j) {
         const int32_t p = p0[j] + slot;
         has[j] = (p < p1[j]) && (col < a.k);
-        c[j] = has[j] ? ld_stream(a.colind + p) : 0;
+        c[j] = has[j] ? ld_mat<C::kNT>(a.colind + p) : 0;
         v[j] = has[j] ? value_at<C>(a, p) : XT(0);
       }
       XT xv[R][VEC];
@@ -247,7 +242,7 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
           for (int32_t p = p0[j] + S + slot; p < p1[j]; p += S) {
             const XT vv = value_at<C>(a, p);
             XT xx[VEC];
-            load_x<XT, VEC>(X + static_cast<int64_t>(ld_stream(a.colind + p)) * a.ldx, xx);
+            load_x<XT, VEC>(X + static_cast<int64_t>(ld_mat<C::kNT>(a.colind + p)) * a.ldx, xx);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
               if (C::kComp && comp) cacc[e].add_prod(vv, xx[e]);
@@ -391,7 +386,7 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
     for (int u = 0; u < kStreamPer; ++u) {
       const int32_t p = s_p0[lo[u]] + (jj[u] - s_off[lo[u]]);
       const bool h = jj[u] < total;
-      cc[u] = h ? ld_stream(a.colind + p) : 0;
+      cc[u] = h ? ld_mat<C::kNT>(a.colind + p) : 0;
       vv[u] = h ? value_at<C>(a, p) : XT(0);
     }
   };
@@ -434,7 +429,7 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
       Comp cc;
       cc.init();
       for (int32_t p = p0; p < p1; ++p)
-        cc.add_prod(value_at<C>(a, p), X[static_cast<int64_t>(ld_stream(a.colind + p)) * a.ldx]);
+        cc.add_prod(value_at<C>(a, p), X[static_cast<int64_t>(ld_mat<C::kNT>(a.colind + p)) * a.ldx]);
       out[0] = static_cast<XT>(cc.value());
     } else {
       out[0] = acc;

@@ -87,3 +87,11 @@ def two_bin_opts(split_above: int, lanes: int, k: int = 1, chunk: int = 512, kah
 def gamma(n, u):
     n = np.asarray(n, dtype=np.float64)
     return n * u / (1.0 - n * u)
+
+
+def stream_mm_opts(k: int, upper: int = 32, chunk: int = 256, kahan: int = 256):
+    """Rows up to `upper` in a stream bin (row groups of KL lanes when k > 1), a
+    wavefront bin up to 256, split rows above."""
+    import paper_1302_1078_amd as spx
+    return spx.PlanOpts.from_dict({"nbins": 3, "upper": [upper, 256], "lanes": [512, 64, 0],
+                                   "split_chunk": chunk, "kahan_len": kahan, "max_k": k})

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import spgen
-from _cases import KINDS, int_valued, matrix, single_bin_opts, to_gpu, two_bin_opts
+from _cases import KINDS, int_valued, matrix, single_bin_opts, stream_mm_opts, to_gpu, two_bin_opts
 
 pytestmark = pytest.mark.gpu
 
@@ -228,7 +228,8 @@ def test_spmm_f64_parity(spx, torch, kind, k):
     ref = oracle.spmm(A, X)
     G = to_gpu(A)
     plans = [None, spx.Plan.for_matrix(G, spx.default_opts(k)),
-             spx.Plan.for_matrix(G, two_bin_opts(64, 64, k, chunk=256))]
+             spx.Plan.for_matrix(G, two_bin_opts(64, 64, k, chunk=256)),
+             spx.Plan.for_matrix(G, stream_mm_opts(k))]
     for ld_pad in (0, 3):
         Xd = torch.zeros((A.n, k + ld_pad), dtype=torch.float64, device="cuda:0")
         Xd[:, :k] = dev_vec(torch, X)
@@ -250,7 +251,8 @@ def test_spmm_exact_inputs_bit_exact(spx, torch, k):
     ref = oracle.spmm(A, X)
     G = to_gpu(A)
     for plan in (None, spx.Plan.for_matrix(G, spx.default_opts(k)),
-                 spx.Plan.for_matrix(G, single_bin_opts(0, k, chunk=256))):
+                 spx.Plan.for_matrix(G, single_bin_opts(0, k, chunk=256)),
+                 spx.Plan.for_matrix(G, stream_mm_opts(k))):
         Y = spx.spmm(G, dev_vec(torch, X), plan=plan).cpu().numpy()
         assert np.array_equal(Y, ref)
 
@@ -273,3 +275,46 @@ def test_spmm_deterministic_split(spx, torch):
     assert plan.info()["segments"] > 1
     Ys = [spx.spmm(G, X, plan=plan).cpu().numpy().view(np.uint64) for _ in range(4)]
     assert all(np.array_equal(Ys[0], Y) for Y in Ys[1:])
+
+
+@pytest.mark.parametrize("per_row", [1, 7, 31, 32])
+@pytest.mark.parametrize("k", [2, 3, 8, 16, 100])
+def test_spmm_equal_rows_stream_plan(spx, torch, per_row, k):
+    """SpMM through a plan whose short-row bin is a stream bin (served by row
+    groups of KL lanes when k > 1): rows of one length, so every slot count
+    ends in a masked partial round at some row; a ragged last tile; bit-exact
+    on integer inputs and within the FP64 bar on uniform ones."""
+    coo = spgen.uniform_rows(1000, 700, per_row, 31)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = to_gpu(A)
+    plan = spx.Plan.for_matrix(G, stream_mm_opts(k))
+    _, off = plan.export_bins()
+    assert off[1] - off[0] == A.m  # every row in the short-row bin
+    X = spgen.uniform(A.n * k, 32).reshape(A.n, k)
+    Y = spx.spmm(G, dev_vec(torch, X), plan=plan).cpu().numpy()
+    ref = oracle.spmm(A, X)
+    for j in range(k):
+        assert oracle.rel2(Y[:, j], ref[:, j]) <= TOL_F64, (per_row, k, j)
+    Ai = int_valued(A, 33)
+    Gi = to_gpu(Ai)
+    Xi = spgen.small_ints(A.n * k, 34).reshape(A.n, k)
+    Yi = spx.spmm(Gi, dev_vec(torch, Xi), plan=spx.Plan.for_matrix(Gi, stream_mm_opts(k))).cpu().numpy()
+    assert np.array_equal(Yi, oracle.spmm(Ai, Xi))
+
+
+def test_spmm_stream_deterministic_and_empty_rows(spx, torch):
+    A = matrix("empty_rows", 7)
+    G = to_gpu(A)
+    k = 16
+    X = dev_vec(torch, spgen.uniform(A.n * k, 8).reshape(A.n, k))
+    plan = spx.Plan.for_matrix(G, stream_mm_opts(k))
+    Y0 = torch.full((A.m, k), float("nan"), dtype=torch.float64, device="cuda:0")
+    spx.spmm(G, X, Y=Y0, plan=plan)
+    ref = oracle.spmm(A, X.cpu().numpy())
+    Yn = Y0.cpu().numpy()
+    assert np.isfinite(Yn).all()  # empty rows written as zeros
+    assert (Yn[A.row_lengths() == 0] == 0.0).all()
+    for j in range(k):
+        assert oracle.rel2(Yn[:, j], ref[:, j]) <= TOL_F64
+    Ys = [spx.spmm(G, X, plan=plan).cpu().numpy().view(np.uint64) for _ in range(4)]
+    assert all(np.array_equal(Ys[0], y) for y in Ys[1:])

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import spgen
-from _cases import gamma, int_valued, matrix, single_bin_opts, to_gpu, two_bin_opts
+from _cases import gamma, int_valued, matrix, single_bin_opts, stream_mm_opts, to_gpu, two_bin_opts
 
 pytestmark = pytest.mark.gpu
 
@@ -94,11 +94,14 @@ def test_precision_spmm_bounds(spx, torch, vdtype, k):
     G, A5 = quantised(A, vdtype, torch)
     Y5 = oracle.spmm(A5, Xq.astype(np.float64))
     L = A.row_lengths()
-    plan = spx.Plan.for_matrix(G, spx.default_opts(k, torch.float32))
-    Y = spx.spmm(G, dev(torch, Xq), plan=plan).cpu().numpy()
-    for j in (0, k // 2, k - 1):
-        S = oracle.spmv_abs(A5, Xq[:, j].astype(np.float64))
-        check_bound(Y[:, j], Y5[:, j], S, L, 256, (vdtype, k, j))
+    # default plan; and a plan with kahan_len 4, so that most rows take the
+    # compensated path
+    for kahan, opts in [(256, spx.default_opts(k, torch.float32)), (4, stream_mm_opts(k, kahan=4))]:
+        plan = spx.Plan.for_matrix(G, opts)
+        Y = spx.spmm(G, dev(torch, Xq), plan=plan).cpu().numpy()
+        for j in (0, k // 2, k - 1):
+            S = oracle.spmv_abs(A5, Xq[:, j].astype(np.float64))
+            check_bound(Y[:, j], Y5[:, j], S, L, kahan, (vdtype, k, j, kahan))
 
 
 def test_compensated_sum_pin(spx, torch):
