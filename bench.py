@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the unflushed (warm) calls, so a kernel trace holds flushed calls only")
     ap.add_argument("--forms", default="c0,c2,c3,c4", help="comma list of extra workloads")
     ap.add_argument("--form-steps", type=int, default=20)
     return ap.parse_args()
@@ -368,14 +370,18 @@ def main():
     wall = time.perf_counter() - w0
     tv, tm = t[:, 0], t[:, 1]
     t_step = float(tv.mean() + tm.mean())
-    tw = Timer(torch, dev, False).run(step, 20, 2)
-    tvw, tmw = float(tw[:, 0].mean()), float(tw[:, 1].mean())
+    if args.no_warm:
+        tvw = tmw = float("nan")
+    else:
+        tw = Timer(torch, dev, False).run(step, 20, 2)
+        tvw, tmw = float(tw[:, 0].mean()), float(tw[:, 1].mean())
 
     def stats(ts, flops, b, warm):
         return {"ms": ts.mean() * 1e3, "ms_median": float(np.median(ts)) * 1e3, "ms_min": float(ts.min()) * 1e3,
                 "gflops": flops / ts.mean() / 1e9, "eff_gbs": b / ts.mean() / 1e9,
-                "frac_hbm": b / ts.mean() / 1e9 / PEAK_HBM_GBS, "bytes": b, "warm_ms": warm * 1e3,
-                "warm_eff_gbs": b / warm / 1e9}
+                "frac_hbm": b / ts.mean() / 1e9 / PEAK_HBM_GBS, "bytes": b,
+                "warm_ms": None if warm != warm else warm * 1e3,
+                "warm_eff_gbs": None if warm != warm else b / warm / 1e9}
 
     detail = {"spmv": stats(tv, flops_v, bytes_v, tvw), "spmm": dict(stats(tm, flops_m, bytes_m, tmw), k=k),
               "plans": {"spmv": plan_v.info(), "spmm": plan_m.info()}, "flushed": not args.no_flush,

@@ -215,7 +215,7 @@ extern "C" spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan
   if (k == 1) {
     // SpMV: short rows streamed per workgroup, then a wavefront, a workgroup
     // per row, and split segments for the longest rows.
-    const int32_t upper[] = {32, 128, 2048, 0};
+    const int32_t upper[] = {64, 512, 2048, 0};
     const int32_t lanes[] = {SPX_LANES_STREAM, 64, 256, 0};
     o->nbins = 4;
     for (int b = 0; b < 4; ++b) {
@@ -225,8 +225,8 @@ extern "C" spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan
     o->split_chunk = (vtype == SPX_F64) ? 4096 : 8192;
   } else {
     // SpMM: one X row per KL lanes; more nonzero slots for longer rows.
-    const int32_t upper[] = {8, 32, 128, 512, 0};
-    const int32_t lanes[] = {1, 16, 64, 256, 0};
+    const int32_t upper[] = {8, 32, 128, 1024, 0};
+    const int32_t lanes[] = {1, 8, 32, 64, 0};
     o->nbins = 5;
     for (int b = 0; b < 5; ++b) {
       o->upper[b] = upper[b];

@@ -11,12 +11,15 @@
 namespace spx {
 namespace prod {
 
-// Independent nonzeros per lane and round.  SPX_UNROLL overrides it at build
-// time (for unroll-depth sweeps).
+// Independent nonzeros per lane and round (SpMV; SPX_UNROLL_MM for SpMM).
+// Both can be overridden at build time for unroll-depth sweeps.
 #ifndef SPX_UNROLL
 #define SPX_UNROLL 4
 #endif
 constexpr int kUnroll = SPX_UNROLL;
+#ifndef SPX_UNROLL_MM
+#define SPX_UNROLL_MM 4
+#endif
 
 template <typename VT_, typename XT_, int KL_, int VEC_>
 struct Cfg {
@@ -29,6 +32,7 @@ struct Cfg {
   // SpMV streams colind / values non-temporally; SpMM row groups revisit
   // their lines (see ld_mat)
   static constexpr bool kNT = (KL_ * VEC_ == 1);
+  static constexpr int U = (KL_ * VEC_ == 1) ? kUnroll : SPX_UNROLL_MM;
 };
 
 template <typename T, int N>
@@ -70,34 +74,63 @@ __device__ __forceinline__ typename C::XT value_at(const ProdArgs& a, int32_t p)
 }
 
 // Accumulate the nonzeros p = p0 + slot, p0 + slot + S, ... < p1 of one row
-// into acc (plain) or cacc (compensated) for the VEC columns at `col`.
-// Every round issues the loads of kUnroll nonzeros before using any; the
-// last round is masked rather than finished one nonzero at a time, so a slot
-// with n nonzeros waits for ceil(n / kUnroll) gather round trips.  Products
-// are added in ascending p either way.
+// into acc (plain) or cacc (compensated) for the VEC columns at `col`
+// (lanes with col >= k take part in the shared loads and gather nothing).
+// Every round issues the loads of U nonzeros before using any; the last
+// round is masked rather than finished one nonzero at a time, so a slot with
+// n nonzeros waits for ceil(n / U) gather round trips.  Products are added in
+// ascending p either way.
+// In SpMM (KL > 1) the KL lanes of a group need the same colind / values:
+// lane kl loads element kl (kl + KL, ...) of the round and the group shares
+// them through ds_bpermute, so a round costs the texture addresser U lanes
+// of index loads instead of U x KL (the address unit, not HBM, bounds the
+// short-row SpMM).
 template <class C, int S>
 __device__ __forceinline__ void accumulate(const ProdArgs& a, int32_t p0, int32_t p1, int slot,
                                            int col, bool comp, typename C::AT (&acc)[C::VEC],
                                            Comp (&cacc)[C::VEC]) {
   using XT = typename C::XT;
   constexpr int VEC = C::VEC;
-  constexpr int U = kUnroll;
+  constexpr int U = C::U;
   const XT* X = static_cast<const XT*>(a.X) + col;
   const int64_t ldx = a.ldx;
+  const bool colok = col < a.k;
   for (int32_t p = p0 + slot; p < p1; p += U * S) {
     bool h[U];
     int32_t c[U];
     XT v[U];
     XT xv[U][VEC];
+    if constexpr (C::KL > 1) {
+      constexpr int KL = C::KL;
+      constexpr int PER = (U + KL - 1) / KL;
+      const int lane = threadIdx.x % kWave;
+      const int kl = lane % KL, base = lane - kl;
+      int32_t cl[PER];
+      XT vl[PER];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      h[u] = p + u * S < p1;
-      c[u] = h[u] ? ld_mat<C::kNT>(a.colind + p + u * S) : 0;
-      v[u] = h[u] ? value_at<C>(a, p + u * S) : XT(0);
+      for (int j = 0; j < PER; ++j) {
+        const int u = kl + j * KL;
+        const bool hl = u < U && p + u * S < p1;
+        cl[j] = hl ? ld_mat<C::kNT>(a.colind + p + u * S) : 0;
+        vl[j] = hl ? value_at<C>(a, p + u * S) : XT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        h[u] = p + u * S < p1;
+        c[u] = __shfl(cl[u / KL], base + u % KL, kWave);
+        v[u] = __shfl(vl[u / KL], base + u % KL, kWave);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        h[u] = p + u * S < p1;
+        c[u] = h[u] ? ld_mat<C::kNT>(a.colind + p + u * S) : 0;
+        v[u] = h[u] ? value_at<C>(a, p + u * S) : XT(0);
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (h[u]) {
+      if (h[u] && colok) {
         load_x<XT, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
       } else {
 #pragma unroll
@@ -271,7 +304,7 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
         acc[e] = AT(0);
         cacc[e].init();
       }
-      if (col < a.k) accumulate<C, S>(a, p0, p1, slot, col, comp, acc, cacc);
+      accumulate<C, S>(a, p0, p1, slot, col, comp, acc, cacc);  // every lane: shared loads
 
       if constexpr (GG <= kWave) {
         finish_small<C, GG>(a, active, comp, slot, col, row, acc, cacc, nt);
@@ -470,7 +503,7 @@ __device__ __forceinline__ void do_split(const ProdArgs& a, const BinDesc& d, in
       acc[e] = AT(0);
       cacc[e].init();
     }
-    if (col < a.k) accumulate<C, S>(a, p0, p1, slot, col, comp, acc, cacc);
+    accumulate<C, S>(a, p0, p1, slot, col, comp, acc, cacc);  // every lane: shared loads
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       double v;
