@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the unflushed (warm) calls, so a kernel trace holds flushed calls only")
-    ap.add_argument("--forms", default="c0,c2,c3,c4", help="comma list of extra workloads")
+    ap.add_argument("--forms", default="c0,c2,c3,c4",
+                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep)")
     ap.add_argument("--form-steps", type=int, default=20)
     return ap.parse_args()
 
@@ -223,6 +224,99 @@ def bench_c2(ctx, A1=None):
         del ref
     out["note"] = ("FP32/BF16 values with FP32 x/y and FP32 accumulation; rows longer than 256 use "
                    "compensated sums with an FP64 cross-lane reduction")
+    return out
+
+
+# ---------------------------------------------------------------- k sweep (SpMM variants)
+
+def bench_ksweep(ctx, A1=None):
+    """SpMM variant ablation and k sweep (Sec. 5): for k in 1..64, X row-major
+    with vector X loads (the k-specialised kernel), with scalar X loads (the
+    generic kernel), with non-temporal Y stores (the paper's NRNGO-store
+    variant), and X column-major served as k SpMVs over contiguous columns.
+    FP64, flushed calls."""
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    from paper_1302_1078_amd import _lib
+    out = {}
+    mats = [("stencil27_128", upload(torch, spx, spgen.workload_c2_stencil(0), dev))]
+    if A1 is not None:
+        mats.append(("powerlaw_1M", A1))
+    for name, A in mats:
+        m, n, nnz = A.m, A.n, A.nnz
+        pv = spx.Plan.for_matrix(A, spx.default_opts(1))
+        rows = {}
+        for k in (1, 2, 4, 8, 16, 32, 64):
+            X = torch.from_numpy(spgen.uniform(n * k, 11, spgen.TAG_X).reshape(n, k)).to(dev)
+            Y = torch.empty((m, k), dtype=torch.float64, device=dev)
+            b = app_bytes(m, n, nnz, k)
+            r = {}
+            nt = _lib.SPX_FLAG_NO_NT_STORE
+            variants = [("vector", nt), ("scalar_x", nt | _lib.SPX_FLAG_SCALAR_X), ("vector_nt_store", 0)]
+            ref = None
+            for vname, flags in variants:
+                o = spx.default_opts(k)
+                o.flags = flags
+                plan = spx.Plan.for_matrix(A, o)
+                fn = lambda plan=plan: spx.spmm(A, X, Y=Y, plan=plan)  # noqa: E731
+                t = float(ctx["timer"].run([fn], ctx["fsteps"], 3)[:, 0].mean())
+                if ref is None:
+                    ref = Y.clone()
+                    err = 0.0
+                else:
+                    err = float((Y - ref).abs().max() / ref.abs().max().clamp_min(1e-300))
+                r[vname] = {"us": t * 1e6, "gflops": 2 * nnz * k / t / 1e9, "eff_gbs": b / t / 1e9,
+                            "max_rel_diff_vs_vector": err}
+                del plan
+            XT = X.t().contiguous()
+            YT = torch.empty((k, m), dtype=torch.float64, device=dev)
+
+            def colmajor():
+                for j in range(k):
+                    spx.spmv(A, XT[j], y=YT[j], plan=pv)
+            t = float(ctx["timer"].run([colmajor], max(3, ctx["fsteps"] // 4), 1)[:, 0].mean())
+            err = float((YT.t() - ref).abs().max() / ref.abs().max().clamp_min(1e-300))
+            r["colmajor_k_spmv"] = {"us": t * 1e6, "gflops": 2 * nnz * k / t / 1e9, "eff_gbs": b / t / 1e9,
+                                    "max_rel_diff_vs_vector": err}
+            rows[f"k{k}"] = r
+            del X, Y, XT, YT, ref
+            torch.cuda.empty_cache()
+        out[name] = {"m": m, "nnz": nnz, "results": rows}
+    return out
+
+
+# ---------------------------------------------------------------- occupancy sweep
+
+def bench_occupancy(ctx, A1=None):
+    """Latency versus bandwidth (Sec. 4.2): the same products with at most
+    1..8 workgroups per CU (LDS padding), the GPU analogue of the paper's
+    threads-per-core scaling.  FP64, flushed calls, default plans."""
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    out = {}
+    mats = [("stencil27_128", upload(torch, spx, spgen.workload_c2_stencil(0), dev))]
+    if A1 is not None:
+        mats.append(("powerlaw_1M", A1))
+    for name, A in mats:
+        m, n, nnz = A.m, A.n, A.nnz
+        rows = {}
+        for k in (1, 16):
+            X = torch.from_numpy(spgen.uniform(n * k, 12, spgen.TAG_X).reshape(n, k)).to(dev)
+            x = X[:, 0].contiguous()
+            Y = torch.empty((m, k), dtype=torch.float64, device=dev)
+            b = app_bytes(m, n, nnz, k)
+            r = {}
+            for occ in (1, 2, 3, 4, 6, 8, 0):
+                o = spx.default_opts(k)
+                o.occupancy = occ
+                plan = spx.Plan.for_matrix(A, o)
+                if k == 1:
+                    fn = lambda plan=plan: spx.spmv(A, x, y=Y[:, 0], plan=plan)  # noqa: E731
+                else:
+                    fn = lambda plan=plan: spx.spmm(A, X, Y=Y, plan=plan)  # noqa: E731
+                t = float(ctx["timer"].run([fn], ctx["fsteps"], 3)[:, 0].mean())
+                r[f"wg_per_cu_{occ}" if occ else "uncapped"] = {"us": t * 1e6, "eff_gbs": b / t / 1e9}
+            rows[f"k{k}"] = r
+            del X, x, Y
+        out[name] = rows
     return out
 
 
@@ -428,6 +522,10 @@ def main():
                     forms[name] = bench_c3(ctx)
                 elif name == "c4":
                     forms[name] = bench_c4(ctx)
+                elif name == "ksweep":
+                    forms[name] = bench_ksweep(ctx, A)
+                elif name == "occupancy":
+                    forms[name] = bench_occupancy(ctx, A)
                 forms[name]["bench_s"] = round(time.time() - f0, 1)
             except Exception as e:  # a failing form is reported, not hidden
                 forms[name] = {"error": repr(e)}

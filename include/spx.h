@@ -80,7 +80,13 @@ typedef struct spx_plan_opts {
   int32_t kahan_len;   /* FP32 accumulation: rows with L > kahan_len are compensated */
   int32_t max_k;       /* widest SpMM right-hand side the plan serves (>= 1) */
   uint32_t flags;      /* SPX_FLAG_* */
-  int32_t reserved[4];
+  int32_t occupancy;   /* 0, or the most workgroups per CU the product launch may hold
+                        * (1..8): enforced by padding each workgroup's LDS, for
+                        * latency / occupancy sweeps (the GPU analogue of the paper's
+                        * threads-per-core scaling, Sec. 4.2).  Rejected with
+                        * SPX_ERR_UNSUPPORTED at launch if the device's LDS limits
+                        * cannot express it. */
+  int32_t reserved[3];
 } spx_plan_opts;
 
 typedef struct spx_plan spx_plan;   /* opaque host object */

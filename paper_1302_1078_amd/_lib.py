@@ -33,14 +33,15 @@ class PlanOpts(ctypes.Structure):
         ("kahan_len", ctypes.c_int32),
         ("max_k", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("occupancy", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
     def to_dict(self) -> dict:
         nb = self.nbins
         return {"nbins": nb, "upper": list(self.upper[:nb - 1]), "lanes": list(self.lanes[:nb]),
                 "split_chunk": self.split_chunk, "kahan_len": self.kahan_len,
-                "max_k": self.max_k, "flags": self.flags}
+                "max_k": self.max_k, "flags": self.flags, "occupancy": self.occupancy}
 
     @classmethod
     def from_dict(cls, d: dict) -> "PlanOpts":
@@ -54,6 +55,7 @@ class PlanOpts(ctypes.Structure):
         o.kahan_len = int(d.get("kahan_len", 256))
         o.max_k = int(d.get("max_k", 1))
         o.flags = int(d.get("flags", 0))
+        o.occupancy = int(d.get("occupancy", 0))
         return o
 
 

@@ -50,11 +50,15 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
     return;
   }
   // row groups of G lanes; a bin may give each group several rows (rpg),
-  // taken in the same order as the product kernels
-  const int G = (d.lanes == SPX_LANES_STREAM) ? 1 : d.lanes;  // stream bins: a row per thread
+  // taken in the same order as the product kernels.  A stream bin's 256 rows
+  // per workgroup are served by 32 groups of 8 lanes, 8 rows each, so that
+  // the per-nonzero loads and stores of a row are contiguous across lanes.
+  const bool stream = (d.lanes == SPX_LANES_STREAM);
+  const int G = stream ? 8 : d.lanes;
+  const int rpg = stream ? 8 : d.rpg;  // 32 groups x 8 rows = the bin's 256 rows per workgroup
   const int ng = kWG / G;
-  for (int j = 0; j < d.rpg; ++j) {
-    const int idx = (tile * d.rpg + j) * ng + t / G;
+  for (int j = 0; j < rpg; ++j) {
+    const int idx = (tile * rpg + j) * ng + t / G;
     if (idx >= d.nrows) continue;
     const int32_t row = a.row_perm ? a.row_perm[d.row_begin + idx] : d.row_begin + idx;
     const int32_t p1 = a.rowptr[row + 1];

@@ -102,6 +102,7 @@ struct ProdArgs {
   int32_t chunk;
   int32_t max_k;
   uint32_t flags;
+  int32_t occupancy;         // 0, or the workgroups-per-CU cap of the launch
   int32_t nbins;
   BinDesc bins[SPX_MAX_BINS];
 };

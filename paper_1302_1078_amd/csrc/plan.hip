@@ -191,6 +191,8 @@ spx_status check_opts(const spx_plan_opts* o) {
     return fail(SPX_ERR_INVALID, "split_chunk=%d < 256", o->split_chunk);
   if (o->kahan_len < 0) return fail(SPX_ERR_INVALID, "kahan_len < 0");
   if (o->max_k < 1) return fail(SPX_ERR_INVALID, "max_k < 1");
+  if (o->occupancy < 0 || o->occupancy > 8)
+    return fail(SPX_ERR_INVALID, "occupancy=%d outside [0, 8]", o->occupancy);
   return SPX_OK;
 }
 
@@ -225,8 +227,11 @@ extern "C" spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan
     o->split_chunk = (vtype == SPX_F64) ? 4096 : 8192;
   } else {
     // SpMM: one X row per KL lanes; more nonzero slots for longer rows.
+    // Y rows are written with ordinary stores: non-temporal ones measured
+    // 1-3 % slower for k >= 8 on MI355X (they help neither SpMV nor SpMM).
     const int32_t upper[] = {8, 32, 128, 1024, 0};
     const int32_t lanes[] = {1, 8, 32, 64, 0};
+    o->flags = SPX_FLAG_NO_NT_STORE;
     o->nbins = 5;
     for (int b = 0; b < 5; ++b) {
       o->upper[b] = upper[b];
@@ -411,6 +416,7 @@ void bins_from_plan(const spx_plan* p, ProdArgs& a, int kl) {
   a.max_k = o.max_k;
   a.kahan_len = o.kahan_len;
   a.flags = o.flags;
+  a.occupancy = o.occupancy;
 }
 
 void bins_unbinned(int32_t m, int32_t nnz, int kl, ProdArgs& a) {

@@ -85,18 +85,47 @@ __global__ __launch_bounds__(kWG) void k_product(const ProdArgs a) {
   }
 }
 
+// Dynamic LDS that lets at most `occ` workgroups of kernel `fn` share a CU
+// (each workgroup then holds more than 1/(occ+1) of the CU's LDS).
+spx_status occupancy_lds(const void* fn, int occ, size_t* dyn) {
+  int dev = 0, per_cu = 0, per_block = 0;
+  SPX_HIP(hipGetDevice(&dev));
+  SPX_HIP(hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+  SPX_HIP(hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  hipFuncAttributes at;
+  SPX_HIP(hipFuncGetAttributes(&at, fn));
+  const size_t want = static_cast<size_t>(per_cu) / occ;
+  if (want > static_cast<size_t>(per_block) || want < at.sharedSizeBytes)
+    return fail(SPX_ERR_UNSUPPORTED,
+                "occupancy=%d needs %zu B of LDS per workgroup (static %zu, device limit %d per "
+                "workgroup, %d per CU)",
+                occ, want, static_cast<size_t>(at.sharedSizeBytes), per_block, per_cu);
+  *dyn = want - at.sharedSizeBytes;
+  SPX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(*dyn)));
+  return SPX_OK;
+}
+
+template <class C, bool MR>
+spx_status launch_k(const ProdArgs& a, unsigned grid, hipStream_t st) {
+  size_t dyn = 0;
+  if (a.occupancy > 0) {
+    const spx_status s = occupancy_lds(reinterpret_cast<const void*>(&k_product<C, MR>), a.occupancy, &dyn);
+    if (s != SPX_OK) return s;
+  }
+  k_product<C, MR><<<grid, kWG, dyn, st>>>(a);
+  SPX_LAUNCHED("k_product");
+  return SPX_OK;
+}
+
 template <typename VT, typename XT, int VECMAX>
 spx_status launch_vt(ProdArgs& a, int kl, int vec, unsigned grid, hipStream_t st) {
   bool mr = false;
   for (int i = 0; i < a.nbins; ++i) mr = mr || (a.bins[i].rpg > 1);
-#define SPX_CASE(KL_, VEC_)                                                         \
-  if (kl == KL_ && vec == VEC_) {                                                   \
-    if (KL_ == 1 && VEC_ == 1 && mr)                                                \
-      k_product<Cfg<VT, XT, KL_, VEC_>, true><<<grid, kWG, 0, st>>>(a);             \
-    else                                                                            \
-      k_product<Cfg<VT, XT, KL_, VEC_>, false><<<grid, kWG, 0, st>>>(a);            \
-    SPX_LAUNCHED("k_product");                                                      \
-    return SPX_OK;                                                                  \
+#define SPX_CASE(KL_, VEC_)                                                   \
+  if (kl == KL_ && vec == VEC_) {                                             \
+    if (KL_ == 1 && VEC_ == 1 && mr)                                          \
+      return launch_k<Cfg<VT, XT, KL_, VEC_>, true>(a, grid, st);             \
+    return launch_k<Cfg<VT, XT, KL_, VEC_>, false>(a, grid, st);              \
   }
   SPX_CASE(1, 1) SPX_CASE(2, 1) SPX_CASE(4, 1) SPX_CASE(8, 1) SPX_CASE(16, 1) SPX_CASE(32, 1)
   SPX_CASE(1, VECMAX) SPX_CASE(2, VECMAX) SPX_CASE(4, VECMAX) SPX_CASE(8, VECMAX)

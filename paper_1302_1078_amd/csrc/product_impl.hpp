@@ -291,7 +291,16 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
     const int idx = tile * NG + grp;
     const bool active = idx < d.nrows;
     int32_t row = 0, p0 = 0, p1 = 0;
-    if (active) row_range(a, d, idx, row, p0, p1);
+    if constexpr (KL > 1) {
+      // one lane per group reads the row's id and range; the group shares them
+      if (active && kl == 0) row_range(a, d, idx, row, p0, p1);
+      const int src = (t % kWave) - kl;
+      row = __shfl(row, src, kWave);
+      p0 = __shfl(p0, src, kWave);
+      p1 = __shfl(p1, src, kWave);
+    } else if (active) {
+      row_range(a, d, idx, row, p0, p1);
+    }
     const bool comp = C::kComp && (p1 - p0 > a.kahan_len);
     XT* Y = static_cast<XT*>(a.Y);
 

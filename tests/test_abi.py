@@ -81,10 +81,23 @@ def test_missing_library_fails_loudly(tmp_path):
     assert "LOUD" in r.stdout, r.stderr
 
 
+def test_occupancy_option_checked():
+    """occupancy outside [0, 8] is rejected when the plan is sized (host-side check)."""
+    import ctypes
+    from paper_1302_1078_amd import _lib
+    L = _lib.load()
+    o = _lib.PlanOpts.from_dict({"nbins": 1, "upper": [], "lanes": [64], "max_k": 1, "occupancy": 9})
+    nb = ctypes.c_size_t()
+    assert L.csr_plan_workspace_bytes(100, 1000, ctypes.byref(o), ctypes.byref(nb)) != 0
+    assert b"occupancy" in L.spx_last_error()
+    o.occupancy = 4
+    assert L.csr_plan_workspace_bytes(100, 1000, ctypes.byref(o), ctypes.byref(nb)) == 0
+
+
 def test_plan_opts_roundtrip_and_autotune_cache(tmp_path):
     from paper_1302_1078_amd import _lib, autotune
     d = {"nbins": 3, "upper": [4, 64], "lanes": [4, 64, 0], "split_chunk": 1024, "kahan_len": 256,
-         "max_k": 8, "flags": 0}
+         "max_k": 8, "flags": 0, "occupancy": 3}
     assert _lib.PlanOpts.from_dict(d).to_dict() == d
     p = tmp_path / "c.json"
     p.write_text("{broken")

@@ -318,3 +318,23 @@ def test_spmm_stream_deterministic_and_empty_rows(spx, torch):
         assert oracle.rel2(Yn[:, j], ref[:, j]) <= TOL_F64
     Ys = [spx.spmm(G, X, plan=plan).cpu().numpy().view(np.uint64) for _ in range(4)]
     assert all(np.array_equal(Ys[0], y) for y in Ys[1:])
+
+
+@pytest.mark.parametrize("k", [1, 16])
+def test_occupancy_cap_same_result(spx, torch, k):
+    """The occupancy cap (LDS padding) changes scheduling only: results are
+    bitwise those of the uncapped launch."""
+    A = matrix("powerlaw_sq", 9)
+    G = to_gpu(A)
+    X = spgen.uniform(A.n * k, 10).reshape(A.n, k)
+    Xd = dev_vec(torch, X if k > 1 else X[:, 0])
+    outs = []
+    for occ in (0, 1, 2, 4, 8):
+        o = spx.default_opts(k)
+        o.occupancy = occ
+        plan = spx.Plan.for_matrix(G, o)
+        Y = (spx.spmm(G, Xd, plan=plan) if k > 1 else spx.spmv(G, Xd, plan=plan)).cpu().numpy()
+        outs.append(Y.view(np.uint64))
+    assert all(np.array_equal(outs[0], y) for y in outs[1:])
+    ref = oracle.spmm(A, X) if k > 1 else oracle.spmv(A, X[:, 0])
+    assert oracle.rel2(outs[0].view(np.float64).ravel(), ref.ravel()) <= TOL_F64
