@@ -66,6 +66,10 @@ def lib():
         L.orc_spmv_abs.argtypes = [i32, P, P, P, P, P]
         L.orc_ucld.restype = f64
         L.orc_ucld.argtypes = [i32, P, P, i32, P]
+        L.orc_vector_access.restype = f64
+        L.orc_vector_access.argtypes = [i32, i32, P, P, i32, i32, i32]
+        L.orc_rcm.restype = ctypes.c_int
+        L.orc_rcm.argtypes = [i32, i32, P, P, P]
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -179,6 +183,31 @@ def spmv_abs(A: CSR, x) -> np.ndarray:
 def ucld(A: CSR, line: int = 8) -> float:
     used = np.zeros(1, dtype=np.int64)
     return float(lib().orc_ucld(A.m, _p(A.rowptr), _p(_i32(A.colind)), line, _p(used)))
+
+
+def vector_access(A: CSR, line: int = 16, parts: int = 8, chunk: int = 64) -> float:
+    """Expected number of times x is moved from memory (Sec. 4.2): rows dealt
+    round-robin to `parts` infinite caches in chunks of `chunk` rows."""
+    return float(lib().orc_vector_access(A.m, A.n, _p(A.rowptr), _p(_i32(A.colind)), line, parts, chunk))
+
+
+def rcm(A: CSR) -> np.ndarray:
+    """Reverse Cuthill-McKee order of the pattern of A + A^T (Sec. 4.4);
+    perm[new] = old."""
+    perm = np.empty(A.m, dtype=np.int32)
+    if lib().orc_rcm(A.m, A.n, _p(A.rowptr), _p(_i32(A.colind)), _p(perm)) != 0:
+        raise ValueError("rcm needs a square matrix")
+    return perm
+
+
+def permute(A: CSR, perm) -> CSR:
+    """P A P^T for perm[new] = old (rows and columns renumbered), assembled
+    canonically."""
+    perm = np.asarray(perm, dtype=np.int64)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    rows = np.repeat(np.arange(A.m, dtype=np.int64), np.diff(A.rowptr))
+    return csr_from_coo(A.m, A.n, inv[rows].astype(np.int32), inv[A.colind].astype(np.int32), A.values)
 
 
 def max_threads() -> int:

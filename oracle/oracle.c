@@ -241,4 +241,194 @@ double orc_ucld(int32_t m, const int32_t *rowptr, const int32_t *colind, int32_t
   return used ? sum / (double)used : 0.0;
 }
 
+/* ------------------------------------------------------------------------
+ * Vector access (Sec. 4.2 and Sec. 4.4): the expected number of times the
+ * input vector is moved from memory when rows are dealt to `parts` caches in
+ * chunks of `chunk` consecutive rows, round-robin, each cache infinite.  It is
+ * the number of distinct (part, x cacheline) pairs touched, divided by the
+ * number of x cachelines, ceil(n / line).
+ * ---------------------------------------------------------------------- */
+double orc_vector_access(int32_t m, int32_t n, const int32_t *rowptr, const int32_t *colind,
+                         int32_t line, int32_t parts, int32_t chunk) {
+  int64_t nlines = ((int64_t)n + line - 1) / line;
+  if (nlines == 0) return 0.0;
+  int32_t *seen = (int32_t *)calloc((size_t)nlines, sizeof(int32_t));
+  int64_t pairs = 0;
+  for (int32_t q = 0; q < parts; ++q) {
+    for (int64_t c0 = (int64_t)q * chunk; c0 < m; c0 += (int64_t)parts * chunk) {
+      int64_t c1 = c0 + chunk < m ? c0 + chunk : m;
+      for (int64_t i = c0; i < c1; ++i) {
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+          int64_t ln = colind[p] / line;
+          if (seen[ln] != q + 1) {
+            seen[ln] = q + 1;
+            ++pairs;
+          }
+        }
+      }
+    }
+  }
+  free(seen);
+  return (double)pairs / (double)nlines;
+}
+
+/* ------------------------------------------------------------------------
+ * Reverse Cuthill-McKee ordering (Sec. 4.4 applies it to every matrix; the
+ * algorithm is Cuthill and McKee's breadth-first numbering, reversed).  The
+ * paper used MATLAB's implementation and gives no tie rules, so this reading
+ * fixes them:
+ *   - the graph is the pattern of A + A^T without the diagonal (n x n);
+ *   - components are numbered one after the other; each starts from the
+ *     unnumbered vertex of smallest (degree, index), moved to a
+ *     pseudo-peripheral vertex by George and Liu's rule: build the level
+ *     structure from r, take the vertex of smallest (degree, index) in its
+ *     last level, and move there while that deepens the structure;
+ *   - breadth-first numbering from the start vertex, the unnumbered
+ *     neighbours of each vertex appended in ascending (degree, index);
+ *   - the whole numbering is reversed at the end.
+ * perm[new] = old.  Returns 0, or -1 if the matrix is not square.
+ * ---------------------------------------------------------------------- */
+static const int32_t *orc_rcm_deg; /* qsort has no context argument */
+
+static int orc_by_deg(const void *a, const void *b) {
+  int32_t u = *(const int32_t *)a, v = *(const int32_t *)b;
+  if (orc_rcm_deg[u] != orc_rcm_deg[v]) return orc_rcm_deg[u] < orc_rcm_deg[v] ? -1 : 1;
+  return (u > v) - (u < v);
+}
+
+static int orc_i32_cmp(const void *a, const void *b) {
+  int32_t u = *(const int32_t *)a, v = *(const int32_t *)b;
+  return (u > v) - (u < v);
+}
+
+/* Level structure from r over unnumbered vertices: fills `lv` with the
+ * vertices in breadth-first order, returns the number of levels and sets
+ * [*last0, *last1) to the last level's slice of lv. */
+static int32_t orc_levels(int32_t r, const int64_t *xadj, const int32_t *adj, const char *numbered,
+                          int32_t *mark, int32_t stamp, int32_t *lv, int32_t *last0, int32_t *last1) {
+  int32_t head = 0, tail = 0, nlev = 0;
+  lv[tail++] = r;
+  mark[r] = stamp;
+  while (head < tail) {
+    int32_t lo = head, hi = tail;
+    ++nlev;
+    *last0 = lo;
+    *last1 = hi;
+    for (int32_t t = lo; t < hi; ++t) {
+      int32_t v = lv[t];
+      for (int64_t e = xadj[v]; e < xadj[v + 1]; ++e) {
+        int32_t w = adj[e];
+        if (!numbered[w] && mark[w] != stamp) {
+          mark[w] = stamp;
+          lv[tail++] = w;
+        }
+      }
+    }
+    head = hi;
+  }
+  return nlev;
+}
+
+int orc_rcm(int32_t m, int32_t n, const int32_t *rowptr, const int32_t *colind, int32_t *perm) {
+  if (m != n) return -1;
+  if (n == 0) return 0;
+  /* symmetric adjacency: count both directions, fill, sort, drop repeats */
+  int32_t *cnt = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+      if (colind[p] != i) {
+        ++cnt[i];
+        ++cnt[colind[p]];
+      }
+  int64_t *xadj = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  xadj[0] = 0;
+  for (int32_t i = 0; i < n; ++i) xadj[i + 1] = xadj[i] + cnt[i];
+  int32_t *adj = (int32_t *)malloc((size_t)(xadj[n] > 0 ? xadj[n] : 1) * sizeof(int32_t));
+  int64_t *fill = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  for (int32_t i = 0; i < n; ++i) fill[i] = xadj[i];
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+      int32_t j = colind[p];
+      if (j != i) {
+        adj[fill[i]++] = j;
+        adj[fill[j]++] = i;
+      }
+    }
+  /* sort each list, remove repeats, compact */
+  int64_t out = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t b = xadj[i], e = xadj[i + 1];
+    qsort(adj + b, (size_t)(e - b), sizeof(int32_t), orc_i32_cmp);
+    int64_t start = out;
+    for (int64_t t = b; t < e; ++t)
+      if (t == b || adj[t] != adj[t - 1]) adj[out++] = adj[t];
+    xadj[i] = start;
+    cnt[i] = (int32_t)(out - start); /* degree */
+  }
+  xadj[n] = out;
+  for (int32_t i = n - 1; i >= 0; --i) xadj[i + 1] = xadj[i] + cnt[i];
+  xadj[0] = 0;
+  /* xadj was rebuilt from degrees: lists are contiguous in vertex order */
+  orc_rcm_deg = cnt;
+  int32_t *bydeg = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  for (int32_t i = 0; i < n; ++i) bydeg[i] = i;
+  qsort(bydeg, (size_t)n, sizeof(int32_t), orc_by_deg);
+  char *numbered = (char *)calloc((size_t)n, 1);
+  int32_t *mark = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+  int32_t *lv = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *order = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *nb = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t pos = 0, scan = 0, stamp = 0;
+  while (pos < n) {
+    while (numbered[bydeg[scan]]) ++scan;
+    int32_t r = bydeg[scan];
+    int32_t l0, l1;
+    int32_t depth = orc_levels(r, xadj, adj, numbered, mark, ++stamp, lv, &l0, &l1);
+    for (;;) {
+      int32_t x = lv[l0];
+      for (int32_t t = l0 + 1; t < l1; ++t) {
+        int32_t v = lv[t];
+        if (cnt[v] < cnt[x] || (cnt[v] == cnt[x] && v < x)) x = v;
+      }
+      int32_t k0, k1;
+      int32_t d2 = orc_levels(x, xadj, adj, numbered, mark, ++stamp, lv, &k0, &k1);
+      if (d2 > depth) {
+        r = x;
+        depth = d2;
+        l0 = k0;
+        l1 = k1;
+      } else {
+        break;
+      }
+    }
+    /* breadth-first numbering from r */
+    int32_t head = pos;
+    order[pos++] = r;
+    numbered[r] = 1;
+    while (head < pos) {
+      int32_t v = order[head++];
+      int32_t k = 0;
+      for (int64_t e = xadj[v]; e < xadj[v + 1]; ++e)
+        if (!numbered[adj[e]]) nb[k++] = adj[e];
+      qsort(nb, (size_t)k, sizeof(int32_t), orc_by_deg);
+      for (int32_t t = 0; t < k; ++t) {
+        numbered[nb[t]] = 1;
+        order[pos++] = nb[t];
+      }
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) perm[i] = order[n - 1 - i];
+  free(cnt);
+  free(xadj);
+  free(adj);
+  free(fill);
+  free(bydeg);
+  free(numbered);
+  free(mark);
+  free(lv);
+  free(order);
+  free(nb);
+  return 0;
+}
+
 int orc_max_threads(void) { return omp_get_max_threads(); }

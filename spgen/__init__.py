@@ -243,6 +243,17 @@ def shuffled(coo: COO, seed: int) -> COO:
 
 # ---------------------------------------------------------------- named workloads
 
+def relabeled(coo: COO, seed: int) -> COO:
+    """Rows and columns renumbered by one seeded random permutation (P A P^T,
+    square matrices): a banded matrix loses its band.  Old vertex i becomes
+    label[i]."""
+    if coo.m != coo.n:
+        raise ValueError("relabeling needs a square matrix")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    label = rng.permutation(coo.m).astype(np.int32)
+    return COO(coo.m, coo.n, label[coo.r], label[coo.c], coo.v.copy(), dict(coo.info, relabeled=seed))
+
+
 def workload_c0(seed: int = 0) -> COO:
     """10,000 x 10,000, 10 distinct uniform columns per row, values U[-1,1)."""
     return uniform_rows(10_000, 10_000, 10, seed)

@@ -336,3 +336,154 @@ def test_compensated_sum_pin_values():
     assert s32 == np.float32(1.0)
     A = oracle.csr_from_coo(1, terms.size, np.zeros(terms.size), np.arange(terms.size), terms)
     assert oracle.spmv(A, np.ones(terms.size))[0] == 1.0001220703125 == 1 + 2.0 ** -13
+
+
+# ---------------------------------------------------------------- RCM and vector access (Sec. 4.4, Sec. 4.2)
+
+def sym_adj(A):
+    """Neighbour sets of the pattern of A + A^T without the diagonal (brute force)."""
+    nb = [set() for _ in range(A.n)]
+    for i in range(A.m):
+        for p in range(A.rowptr[i], A.rowptr[i + 1]):
+            j = int(A.colind[p])
+            if j != i:
+                nb[i].add(j)
+                nb[j].add(i)
+    return nb
+
+
+def bandwidth(A):
+    if A.nnz == 0:
+        return 0
+    return int(np.abs(A.row_of().astype(np.int64) - A.colind).max())
+
+
+def check_cm_order(nb, order):
+    """Breadth-first numbering invariants of Cuthill-McKee: every vertex but a
+    component's first has an earlier neighbour; the position of the earliest
+    such neighbour (its parent) never decreases; siblings come in ascending
+    (degree, index); a component is numbered before the next one starts."""
+    pos = {v: t for t, v in enumerate(order)}
+    deg = [len(s) for s in nb]
+    last_parent = -1
+    prev = None
+    for t, v in enumerate(order):
+        earlier = [pos[w] for w in nb[v] if pos[w] < t]
+        if not earlier:  # a new component: everything before it is closed
+            assert all(pos[w] < t for u in order[:t] for w in nb[u]), t
+            last_parent, prev = -1, None
+            continue
+        par = min(earlier)
+        assert par >= last_parent, (t, par, last_parent)
+        if par == last_parent:
+            assert (deg[prev], prev) < (deg[v], v), (prev, v)
+        last_parent, prev = par, v
+
+
+def test_rcm_is_a_permutation_and_cm_order():
+    rng = np.random.default_rng(40)
+    for n, nnz in [(1, 1), (7, 12), (60, 150), (300, 900)]:
+        r, c, v = rand_coo(rng, n, n, nnz)
+        A = oracle.csr_from_coo(n, n, r, c, v)
+        perm = oracle.rcm(A)
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        check_cm_order(sym_adj(A), list(perm[::-1]))
+
+
+def test_rcm_diagonal_and_empty():
+    n = 9
+    A = oracle.csr_from_coo(n, n, np.arange(n, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    # every vertex is its own component, taken in (degree 0, index) order, then reversed
+    assert np.array_equal(oracle.rcm(A), np.arange(n)[::-1])
+    E = oracle.csr_from_coo(0, 0, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert oracle.rcm(E).size == 0
+    with pytest.raises(ValueError):
+        oracle.rcm(oracle.csr_from_coo(2, 3, np.zeros(1, np.int32), np.ones(1, np.int32), np.ones(1)))
+
+
+def test_rcm_recovers_relabeled_path_and_stencils():
+    """A relabeled path regains bandwidth 1; relabeled 2D / 3D stencils come
+    back within the breadth-first bound 2w - 1 (w = widest level), far below
+    the relabeled bandwidth (Sec. 4.4: RCM narrows the band)."""
+    n = 500
+    i = np.arange(n - 1, dtype=np.int32)
+    path = spgen.COO(n, n, np.concatenate([i, i + 1]), np.concatenate([i + 1, i]), np.ones(2 * (n - 1)), {})
+    for coo, w_max in [(path, 1), (spgen.stencil5(30, 20, 1), 20), (spgen.stencil3d(8, 7, 6, 7, 2), None)]:
+        R = spgen.relabeled(coo, 5)
+        A = oracle.csr_from_coo(R.m, R.n, R.r, R.c, R.v)
+        perm = oracle.rcm(A)
+        B = oracle.permute(A, perm)
+        nb = sym_adj(A)
+        order = list(perm[::-1])
+        check_cm_order(nb, order)
+        # level widths of the breadth-first structure from the first vertex
+        level = {order[0]: 0}
+        frontier = [order[0]]
+        while frontier:
+            nxt = []
+            for u in frontier:
+                for w in nb[u]:
+                    if w not in level:
+                        level[w] = level[u] + 1
+                        nxt.append(w)
+            frontier = nxt
+        widths = np.bincount(list(level.values()))
+        bw = bandwidth(B)
+        assert bw <= 2 * widths.max() - 1
+        assert bw < bandwidth(A) / 4
+        if w_max is not None:
+            assert widths.max() <= w_max
+    # the path: a peripheral start and bandwidth exactly 1
+    Rp = spgen.relabeled(path, 5)
+    Ap = oracle.csr_from_coo(n, n, Rp.r, Rp.c, Rp.v)
+    assert bandwidth(oracle.permute(Ap, oracle.rcm(Ap))) == 1
+
+
+def test_rcm_components_contiguous():
+    # two relabeled paths of 40 and 25 vertices plus 3 isolated vertices
+    a = np.arange(39, dtype=np.int32)
+    b = np.arange(40, 64, dtype=np.int32)
+    r = np.concatenate([a, a + 1, b, b + 1])
+    c = np.concatenate([a + 1, a, b + 1, b])
+    n = 68
+    R = spgen.relabeled(spgen.COO(n, n, r, c, np.ones(r.size), {}), 3)
+    A = oracle.csr_from_coo(n, n, R.r, R.c, R.v)
+    perm = oracle.rcm(A)
+    nb = sym_adj(A)
+    comp = np.full(n, -1)
+    for s0 in range(n):
+        if comp[s0] < 0:
+            stack = [s0]
+            comp[s0] = s0
+            while stack:
+                u = stack.pop()
+                for w in nb[u]:
+                    if comp[w] < 0:
+                        comp[w] = s0
+                        stack.append(w)
+    labels = comp[perm]
+    runs = [labels[0]] + [labels[t] for t in range(1, n) if labels[t] != labels[t - 1]]
+    assert len(runs) == len(set(runs)) == 5  # each component in one run
+    assert bandwidth(oracle.permute(A, perm)) == 1
+
+
+def test_vector_access_brute_force_and_closed_forms():
+    rng = np.random.default_rng(41)
+    for m, n, nnz, line, parts, chunk in [(50, 70, 300, 4, 3, 5), (200, 130, 900, 16, 8, 7), (10, 10, 0, 4, 2, 3)]:
+        r, c, v = rand_coo(rng, m, n, nnz)
+        A = oracle.csr_from_coo(m, n, r, c, v)
+        pairs = set()
+        for i in range(m):
+            q = (i // chunk) % parts
+            for p in range(A.rowptr[i], A.rowptr[i + 1]):
+                pairs.add((q, int(A.colind[p]) // line))
+        expect = len(pairs) / -(-n // line)
+        assert oracle.vector_access(A, line, parts, chunk) == expect
+    # a diagonal matrix moves x once; a dense one once per part
+    n = 512
+    D = oracle.csr_from_coo(n, n, np.arange(n, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    assert oracle.vector_access(D, 16, 8, 64) == 1.0
+    rr, cc = np.meshgrid(np.arange(64, dtype=np.int32), np.arange(48, dtype=np.int32), indexing="ij")
+    F = oracle.csr_from_coo(64, 48, rr.ravel(), cc.ravel(), np.ones(rr.size))
+    assert oracle.vector_access(F, 16, 8, 8) == 8.0
+    assert oracle.vector_access(F, 16, 8, 64) == 1.0
