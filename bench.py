@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the unflushed (warm) calls, so a kernel trace holds flushed calls only")
     ap.add_argument("--forms", default="c0,c2,c3,c4",
-                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep)")
+                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep; rcm = RCM ordering)")
     ap.add_argument("--form-steps", type=int, default=20)
     return ap.parse_args()
 
@@ -320,6 +320,59 @@ def bench_occupancy(ctx, A1=None):
     return out
 
 
+# ---------------------------------------------------------------- RCM ordering (Sec. 4.4)
+
+def bench_rcm(ctx, A1=None):
+    """Products before and after reverse Cuthill-McKee ordering (Sec. 4.4):
+    the 27-point stencil in its natural order, randomly relabeled, and the
+    relabeled matrix reordered by RCM; the power-law matrix as generated and
+    reordered.  Reports time, UCLD and vector access (x lines of 128 B, rows
+    dealt to 8 XCD caches in contiguous eighths, the tile map's layout)."""
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    out = {}
+    st = spgen.workload_c2_stencil(0)
+    stencil = upload(torch, spx, st, dev)
+    relab = upload(torch, spx, spgen.relabeled(st, 1), dev)
+    del st
+    mats = [("stencil27_128", [("natural", stencil), ("relabeled", relab)])]
+    if A1 is not None:
+        mats.append(("powerlaw_1M", [("natural", A1)]))
+    for name, orders in mats:
+        src_name, src = orders[-1]
+        t0 = time.time()
+        perm = spx.rcm(src)
+        rcm_s = time.time() - t0
+        t0 = time.time()
+        R = spx.permute(src, perm)
+        torch.cuda.synchronize()
+        permute_s = time.time() - t0
+        rows = {}
+        for oname, A in orders + [(f"rcm_of_{src_name}", R)]:
+            m, n, nnz = A.m, A.n, A.nnz
+            r = {"ucld_line16": spx.ucld(A, 16),
+                 "vector_access_8xcd": spx.vector_access(A, 16, 8, -(-m // 8)),
+                 "bandwidth": int((A.colind.long() - torch.repeat_interleave(
+                     torch.arange(m, device=dev), A.rowptr[1:].long() - A.rowptr[:-1].long())).abs().max())}
+            for k in (1, 8):
+                X = torch.from_numpy(spgen.uniform(n * k, 13, spgen.TAG_X).reshape(n, k)).to(dev)
+                plan = spx.Plan.for_matrix(A, spx.default_opts(k))
+                if k == 1:
+                    x = X[:, 0].contiguous()
+                    y = torch.empty(m, dtype=torch.float64, device=dev)
+                    fn = lambda: spx.spmv(A, x, y=y, plan=plan)  # noqa: E731
+                else:
+                    Y = torch.empty((m, k), dtype=torch.float64, device=dev)
+                    fn = lambda: spx.spmm(A, X, Y=Y, plan=plan)  # noqa: E731
+                t = float(ctx["timer"].run([fn], ctx["fsteps"], 3)[:, 0].mean())
+                r[f"k{k}_us"] = t * 1e6
+                r[f"k{k}_gflops"] = 2 * nnz * k / t / 1e9
+            rows[oname] = r
+        out[name] = {"orders": rows, "rcm_host_s": round(rcm_s, 2), "permute_device_s": round(permute_s, 3)}
+        del R, perm
+        torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------- c3
 
 def bench_c3(ctx):
@@ -526,6 +579,8 @@ def main():
                     forms[name] = bench_ksweep(ctx, A)
                 elif name == "occupancy":
                     forms[name] = bench_occupancy(ctx, A)
+                elif name == "rcm":
+                    forms[name] = bench_rcm(ctx, A)
                 forms[name]["bench_s"] = round(time.time() - f0, 1)
             except Exception as e:  # a failing form is reported, not hidden
                 forms[name] = {"error": repr(e)}

@@ -224,6 +224,48 @@ spx_status csr_batch_run(const spx_batch *batch, void *stream);
 spx_status csr_batch_info(const spx_batch *batch, int64_t *ntiles, int32_t *grid, int64_t *nsegments);
 void csr_batch_destroy(spx_batch *batch);
 
+/* ---------------------------------------------------------------- ordering and structure metrics
+ * Reverse Cuthill-McKee ordering (Sec. 4.4: permuting rows and columns to
+ * pull the nonzeros toward the diagonal, applied before the product).  Host
+ * function on host arrays of a square CSR matrix; fills host_perm[new] = old
+ * (a permutation of 0..m-1).  The graph is the pattern of A + A^T without
+ * the diagonal.  Ties are fixed (the paper used MATLAB's routine and states
+ * none): each component starts from the unnumbered vertex of least (degree,
+ * index), moved to a pseudo-peripheral vertex by George and Liu's rule; the
+ * unnumbered neighbours of each vertex follow in ascending (degree, index);
+ * the breadth-first numbering is reversed at the end.  Checks the CSR
+ * structure; SPX_ERR_INVALID for m != n or bad arrays. */
+spx_status csr_rcm(int32_t m, int32_t n, int32_t nnz, const int32_t *host_rowptr,
+                   const int32_t *host_colind, int32_t *host_perm);
+
+/* P A P^T on the device for a device permutation perm[new] = old of
+ * 0..m-1 (square m x m matrix, FP64 values): row i of the result is row
+ * perm[i] of A with every column j renamed to the new index of j; the output
+ * is canonical CSR (columns ascending).  Outputs rowptr_out int32[m+1],
+ * colind_out int32[nnz], values_out f64[nnz]; *nnz_out (device int32)
+ * receives nnz, or -1 if perm is not a permutation.  Workspace:
+ * csr_permute_workspace_bytes.  Asynchronous on `stream`. */
+spx_status csr_permute_workspace_bytes(int32_t m, int32_t nnz, size_t *bytes);
+spx_status csr_permute(int32_t m, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                       const double *values, const int32_t *perm, int32_t *rowptr_out,
+                       int32_t *colind_out, double *values_out, int32_t *nnz_out, void *workspace,
+                       size_t ws_bytes, void *stream);
+
+/* Vector access (Sec. 4.2, Sec. 4.4): the expected number of times x is moved
+ * from memory when rows are dealt round-robin, in chunks of `chunk`
+ * consecutive rows, to `parts` caches that never evict: distinct (part,
+ * x cacheline) pairs divided by ceil(n / line), `line` = x elements per
+ * cacheline.  Host function on host arrays; *out is host. */
+spx_status csr_vector_access(int32_t m, int32_t n, int32_t nnz, const int32_t *host_rowptr,
+                             const int32_t *host_colind, int32_t line, int32_t parts, int32_t chunk,
+                             double *out);
+
+/* Useful cacheline density (Sec. 4.1): the mean over nonempty rows of
+ * L / (line x distinct x cachelines the row touches); columns ascending in
+ * each row.  Host function on host arrays; *out is host. */
+spx_status csr_ucld(int32_t m, int32_t nnz, const int32_t *host_rowptr, const int32_t *host_colind,
+                    int32_t line, double *out);
+
 /* ---------------------------------------------------------------- probes
  * Memory-system probes (the GPU counterparts of the paper's read / write
  * bandwidth microbenchmarks, Sec. 2.1 and 2.2), used to calibrate measured

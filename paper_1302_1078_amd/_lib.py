@@ -102,6 +102,11 @@ SIGNATURES = {
     "csr_batch_run": (ctypes.c_int, [P, P]),
     "csr_batch_info": (ctypes.c_int, [P, P, P, P]),
     "csr_batch_destroy": (None, [P]),
+    "csr_rcm": (ctypes.c_int, [i32, i32, i32, P, P, P]),
+    "csr_permute_workspace_bytes": (ctypes.c_int, [i32, i32, SZ]),
+    "csr_permute": (ctypes.c_int, [i32, i32, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]),
+    "csr_vector_access": (ctypes.c_int, [i32, i32, i32, P, P, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]),
+    "csr_ucld": (ctypes.c_int, [i32, i32, P, P, i32, ctypes.POINTER(ctypes.c_double)]),
     "spx_probe": (ctypes.c_int, [i32, P, P, ctypes.c_size_t, i32, P]),
 }
 

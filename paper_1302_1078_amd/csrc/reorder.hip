@@ -1,0 +1,300 @@
+// reorder.hip -- matrix ordering (paper Sec. 4.4) and the structure metrics
+// it is judged by (Sec. 4.1 UCLD, Sec. 4.2 vector access).
+//
+// csr_rcm is host code: reverse Cuthill-McKee is a breadth-first search, a
+// one-time preprocessing step whose cost the paper leaves out of its timings
+// (Sec. 4.5).  csr_permute applies an ordering on the device (relabel the
+// triplets, then the regular COO -> CSR assembly).
+//
+// RCM reading (the paper used MATLAB's implementation and states no tie
+// rules): graph = pattern of A + A^T without the diagonal; components are
+// numbered in turn, each from the unnumbered vertex of least (degree,
+// index) moved to a pseudo-peripheral vertex by George and Liu's rule (go to
+// the least-(degree, index) vertex of the last BFS level while that makes
+// the level structure deeper); each vertex's unnumbered neighbours are
+// appended in ascending (degree, index); the numbering is reversed at the end.
+#include <stdlib.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace spx {
+namespace {
+
+// Undirected graph of the pattern of A + A^T, self loops dropped, every
+// neighbour list sorted and free of repeats.
+struct SymGraph {
+  std::vector<int64_t> start;  // n + 1
+  std::vector<int32_t> nbr;
+  int32_t degree(int32_t v) const { return static_cast<int32_t>(start[v + 1] - start[v]); }
+};
+
+void build_sym(int32_t n, const int32_t* rowptr, const int32_t* colind, SymGraph& g) {
+  std::vector<int64_t> fill(static_cast<size_t>(n) + 1, 0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+      const int32_t j = colind[p];
+      if (j == i) continue;
+      ++fill[i + 1];
+      ++fill[j + 1];
+    }
+  for (int32_t i = 0; i < n; ++i) fill[i + 1] += fill[i];
+  std::vector<int32_t> raw(static_cast<size_t>(fill[n]));
+  std::vector<int64_t> cur(fill.begin(), fill.end() - 1);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+      const int32_t j = colind[p];
+      if (j == i) continue;
+      raw[cur[i]++] = j;
+      raw[cur[j]++] = i;
+    }
+  g.start.assign(static_cast<size_t>(n) + 1, 0);
+  g.nbr.clear();
+  g.nbr.reserve(raw.size());
+  for (int32_t v = 0; v < n; ++v) {
+    auto b = raw.begin() + fill[v], e = raw.begin() + fill[v + 1];
+    std::sort(b, e);
+    e = std::unique(b, e);
+    g.nbr.insert(g.nbr.end(), b, e);
+    g.start[v + 1] = static_cast<int64_t>(g.nbr.size());
+  }
+}
+
+// Breadth-first level structure from `root` over vertices not yet numbered;
+// `depth` is filled for the vertices reached (and reset by the caller's
+// `touched` list).  Returns the number of levels; `last` gets the deepest level.
+int32_t level_structure(const SymGraph& g, int32_t root, const std::vector<char>& numbered,
+                        std::vector<int32_t>& depth, std::vector<int32_t>& touched,
+                        std::vector<int32_t>& last) {
+  for (int32_t v : touched) depth[v] = -1;
+  touched.clear();
+  depth[root] = 0;
+  touched.push_back(root);
+  size_t head = 0;
+  int32_t deepest = 0;
+  while (head < touched.size()) {
+    const int32_t v = touched[head++];
+    for (int64_t e = g.start[v]; e < g.start[v + 1]; ++e) {
+      const int32_t w = g.nbr[e];
+      if (numbered[w] || depth[w] >= 0) continue;
+      depth[w] = depth[v] + 1;
+      deepest = std::max(deepest, depth[w]);
+      touched.push_back(w);
+    }
+  }
+  last.clear();
+  for (int32_t v : touched)
+    if (depth[v] == deepest) last.push_back(v);
+  return deepest + 1;
+}
+
+}  // namespace
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" spx_status csr_rcm(int32_t m, int32_t n, int32_t nnz, const int32_t* host_rowptr,
+                              const int32_t* host_colind, int32_t* host_perm) {
+  if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_rcm: negative size");
+  if (m != n) return fail(SPX_ERR_INVALID, "csr_rcm: the matrix must be square (m=%d, n=%d)", m, n);
+  if (m == 0) return SPX_OK;
+  if (!host_rowptr || !host_perm || (nnz > 0 && !host_colind))
+    return fail(SPX_ERR_INVALID, "csr_rcm: null pointer");
+  if (host_rowptr[0] != 0 || host_rowptr[m] != nnz)
+    return fail(SPX_ERR_INVALID, "csr_rcm: rowptr[0]=%d, rowptr[m]=%d, nnz=%d", host_rowptr[0],
+                host_rowptr[m], nnz);
+  for (int32_t i = 0; i < m; ++i)
+    if (host_rowptr[i + 1] < host_rowptr[i]) return fail(SPX_ERR_INVALID, "csr_rcm: rowptr decreases at %d", i);
+  for (int32_t p = 0; p < nnz; ++p)
+    if (host_colind[p] < 0 || host_colind[p] >= n)
+      return fail(SPX_ERR_INVALID, "csr_rcm: column %d out of range at %d", host_colind[p], p);
+  try {
+    SymGraph g;
+    build_sym(n, host_rowptr, host_colind, g);
+    auto before = [&g](int32_t a, int32_t b) {
+      const int32_t da = g.degree(a), db = g.degree(b);
+      return da != db ? da < db : a < b;
+    };
+    std::vector<int32_t> seeds(static_cast<size_t>(n));
+    for (int32_t v = 0; v < n; ++v) seeds[v] = v;
+    std::sort(seeds.begin(), seeds.end(), before);
+    std::vector<char> numbered(static_cast<size_t>(n), 0);
+    std::vector<int32_t> depth(static_cast<size_t>(n), -1), touched, last, fresh;
+    std::vector<int32_t> cm;
+    cm.reserve(static_cast<size_t>(n));
+    size_t next_seed = 0;
+    while (cm.size() < static_cast<size_t>(n)) {
+      while (numbered[seeds[next_seed]]) ++next_seed;
+      int32_t root = seeds[next_seed];
+      int32_t levels = level_structure(g, root, numbered, depth, touched, last);
+      for (;;) {  // George-Liu: walk to a pseudo-peripheral vertex
+        const int32_t cand = *std::min_element(last.begin(), last.end(), before);
+        std::vector<int32_t> cand_last;
+        const int32_t cand_levels = level_structure(g, cand, numbered, depth, touched, cand_last);
+        if (cand_levels <= levels) break;
+        root = cand;
+        levels = cand_levels;
+        last.swap(cand_last);
+      }
+      size_t head = cm.size();
+      cm.push_back(root);
+      numbered[root] = 1;
+      while (head < cm.size()) {
+        const int32_t v = cm[head++];
+        fresh.clear();
+        for (int64_t e = g.start[v]; e < g.start[v + 1]; ++e)
+          if (!numbered[g.nbr[e]]) fresh.push_back(g.nbr[e]);
+        std::sort(fresh.begin(), fresh.end(), before);
+        for (int32_t w : fresh) {
+          numbered[w] = 1;
+          cm.push_back(w);
+        }
+      }
+    }
+    std::reverse_copy(cm.begin(), cm.end(), host_perm);
+  } catch (const std::bad_alloc&) {
+    return fail(SPX_ERR_INVALID, "csr_rcm: out of host memory");
+  }
+  return SPX_OK;
+}
+
+extern "C" spx_status csr_vector_access(int32_t m, int32_t n, int32_t nnz, const int32_t* host_rowptr,
+                                        const int32_t* host_colind, int32_t line, int32_t parts,
+                                        int32_t chunk, double* out) {
+  if (m < 0 || n < 0 || nnz < 0 || line < 1 || parts < 1 || chunk < 1 || !out)
+    return fail(SPX_ERR_INVALID, "csr_vector_access: bad argument");
+  if (m > 0 && (!host_rowptr || (nnz > 0 && !host_colind)))
+    return fail(SPX_ERR_INVALID, "csr_vector_access: null pointer");
+  const int64_t lines = (static_cast<int64_t>(n) + line - 1) / line;
+  if (lines == 0) {
+    *out = 0.0;
+    return SPX_OK;
+  }
+  // last_part[l] = 1 + the last part that touched line l; parts are visited
+  // one after the other, so a line is counted once per part
+  std::vector<int32_t> last_part(static_cast<size_t>(lines), 0);
+  int64_t moved = 0;
+  const int64_t stride = static_cast<int64_t>(parts) * chunk;
+  for (int32_t q = 0; q < parts; ++q)
+    for (int64_t b = static_cast<int64_t>(q) * chunk; b < m; b += stride)
+      for (int64_t i = b; i < std::min<int64_t>(b + chunk, m); ++i)
+        for (int32_t p = host_rowptr[i]; p < host_rowptr[i + 1]; ++p) {
+          const int32_t c = host_colind[p];
+          if (c < 0 || c >= n) return fail(SPX_ERR_INVALID, "csr_vector_access: column out of range");
+          int32_t& lp = last_part[c / line];
+          if (lp != q + 1) {
+            lp = q + 1;
+            ++moved;
+          }
+        }
+  *out = static_cast<double>(moved) / static_cast<double>(lines);
+  return SPX_OK;
+}
+
+extern "C" spx_status csr_ucld(int32_t m, int32_t nnz, const int32_t* host_rowptr, const int32_t* host_colind,
+                               int32_t line, double* out) {
+  if (m < 0 || nnz < 0 || line < 1 || !out) return fail(SPX_ERR_INVALID, "csr_ucld: bad argument");
+  if (m > 0 && (!host_rowptr || (nnz > 0 && !host_colind))) return fail(SPX_ERR_INVALID, "csr_ucld: null pointer");
+  double total = 0.0;
+  int64_t rows = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    const int32_t b = host_rowptr[i], e = host_rowptr[i + 1];
+    if (e <= b) continue;
+    // distinct lines of a row with ascending columns: count line changes
+    int64_t touched = 1;
+    for (int32_t p = b + 1; p < e; ++p) touched += (host_colind[p] / line != host_colind[p - 1] / line);
+    total += static_cast<double>(e - b) / (static_cast<double>(line) * static_cast<double>(touched));
+    ++rows;
+  }
+  *out = rows ? total / static_cast<double>(rows) : 0.0;
+  return SPX_OK;
+}
+
+// ---------------------------------------------------------------- device permutation
+
+namespace spx {
+namespace {
+
+__global__ void k_set_i32(int32_t* __restrict__ p, int32_t n, int32_t value) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + 255) / 256); }
+
+__global__ void k_invert(const int32_t* __restrict__ perm, int32_t m, int32_t* __restrict__ inv) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t o = perm[i];
+  if (o >= 0 && o < m) inv[o] = static_cast<int32_t>(i);
+}
+
+// One thread per old row: its triplets keep their positions, with both
+// indices renamed (a row or column whose label is missing stays -1 and is
+// reported by the assembly's range check).
+__global__ void k_relabel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                          const double* __restrict__ values, const int32_t* __restrict__ inv, int32_t m,
+                          int32_t* __restrict__ r, int32_t* __restrict__ c, double* __restrict__ v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t ri = inv[i];
+  for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+    r[p] = ri;
+    c[p] = inv[colind[p]];
+    v[p] = values[p];
+  }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+}  // namespace spx
+
+extern "C" spx_status csr_permute_workspace_bytes(int32_t m, int32_t nnz, size_t* bytes) {
+  if (!bytes || m < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_permute_workspace_bytes: bad argument");
+  size_t coo = 0;
+  spx_status s = csr_from_coo_workspace_bytes(m, m, nnz, &coo);
+  if (s != SPX_OK) return s;
+  *bytes = align256(sizeof(int32_t) * static_cast<size_t>(m)) + 2 * align256(sizeof(int32_t) * static_cast<size_t>(nnz)) +
+           align256(sizeof(double) * static_cast<size_t>(nnz)) + coo;
+  return SPX_OK;
+}
+
+extern "C" spx_status csr_permute(int32_t m, int32_t nnz, const int32_t* rowptr, const int32_t* colind,
+                                  const double* values, const int32_t* perm, int32_t* rowptr_out,
+                                  int32_t* colind_out, double* values_out, int32_t* nnz_out, void* workspace,
+                                  size_t ws_bytes, void* stream) {
+  if (m < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_permute: negative size");
+  if (!rowptr || !rowptr_out || !nnz_out || (m > 0 && !perm) ||
+      (nnz > 0 && (!colind || !values || !colind_out || !values_out)))
+    return fail(SPX_ERR_INVALID, "csr_permute: null pointer");
+  size_t need = 0;
+  spx_status s = csr_permute_workspace_bytes(m, nnz, &need);
+  if (s != SPX_OK) return s;
+  if (!workspace || ws_bytes < need)
+    return fail(SPX_ERR_WORKSPACE, "csr_permute: workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = as_stream(stream);
+  char* w = static_cast<char*>(workspace);
+  int32_t* inv = reinterpret_cast<int32_t*>(w);
+  w += align256(sizeof(int32_t) * static_cast<size_t>(m));
+  int32_t* r = reinterpret_cast<int32_t*>(w);
+  w += align256(sizeof(int32_t) * static_cast<size_t>(nnz));
+  int32_t* c = reinterpret_cast<int32_t*>(w);
+  w += align256(sizeof(int32_t) * static_cast<size_t>(nnz));
+  double* v = reinterpret_cast<double*>(w);
+  w += align256(sizeof(double) * static_cast<size_t>(nnz));
+  if (m > 0) {
+    k_set_i32<<<blocks_for(m), 256, 0, st>>>(inv, m, -1);
+    SPX_LAUNCHED("k_set_i32");
+    k_invert<<<blocks_for(m), 256, 0, st>>>(perm, m, inv);
+    SPX_LAUNCHED("k_invert");
+    k_relabel<<<blocks_for(m), 256, 0, st>>>(rowptr, colind, values, inv, m, r, c, v);
+    SPX_LAUNCHED("k_relabel");
+  }
+  return csr_from_coo(m, m, nnz, r, c, v, rowptr_out, colind_out, values_out, nnz_out, w,
+                      ws_bytes - static_cast<size_t>(w - static_cast<char*>(workspace)), stream);
+}

@@ -287,6 +287,66 @@ def sddmm(A: CSR, dY: torch.Tensor, X: torch.Tensor, plan: Plan | None = None,
     return out
 
 
+# ---------------------------------------------------------------- ordering and metrics
+
+def _host_pattern(A: CSR):
+    rp = A.rowptr.detach().to("cpu", torch.int32).contiguous()
+    ci = A.colind.detach().to("cpu", torch.int32).contiguous()
+    return rp, ci
+
+
+def rcm(A: CSR) -> torch.Tensor:
+    """Reverse Cuthill-McKee order (csr_rcm, host): device int32 perm, perm[new] = old."""
+    rp, ci = _host_pattern(A)
+    perm = torch.empty(A.m, dtype=torch.int32)
+    check(_lib.load().csr_rcm(A.m, A.n, A.nnz, _ptr(rp), _ptr(ci), _ptr(perm)), "csr_rcm")
+    return perm.to(A.device)
+
+
+def permute(A: CSR, perm: torch.Tensor) -> CSR:
+    """P A P^T for a device permutation perm[new] = old (csr_permute; FP64 values)."""
+    L = _lib.load()
+    _dev(perm, A.values)
+    _contig(perm)
+    if A.m != A.n:
+        raise ValueError("permute needs a square matrix")
+    if perm.dtype != torch.int32 or perm.numel() != A.m:
+        raise ValueError("perm must be int32 with m entries")
+    if A.values.dtype != torch.float64:
+        raise TypeError("permute takes FP64 values")
+    nb = ctypes.c_size_t()
+    check(L.csr_permute_workspace_bytes(A.m, A.nnz, ctypes.byref(nb)), "csr_permute")
+    ws = _workspace(nb.value, A.device)
+    rowptr = torch.empty(A.m + 1, dtype=torch.int32, device=A.device)
+    colind = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=A.device)
+    values = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=A.device)
+    nnz_out = torch.empty(1, dtype=torch.int32, device=A.device)
+    check(L.csr_permute(A.m, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(A.values), _ptr(perm),
+                        _ptr(rowptr), _ptr(colind), _ptr(values), _ptr(nnz_out), _ptr(ws), nb.value,
+                        _stream()), "csr_permute")
+    t = int(nnz_out.item())
+    if t < 0:
+        raise ValueError("csr_permute: perm is not a permutation")
+    return CSR(rowptr, colind[:t], values[:t], (A.m, A.n))
+
+
+def vector_access(A: CSR, line: int = 16, parts: int = 8, chunk: int = 64) -> float:
+    """Expected number of times x is moved from memory (csr_vector_access, host)."""
+    rp, ci = _host_pattern(A)
+    out = ctypes.c_double()
+    check(_lib.load().csr_vector_access(A.m, A.n, A.nnz, _ptr(rp), _ptr(ci), line, parts, chunk,
+                                        ctypes.byref(out)), "csr_vector_access")
+    return out.value
+
+
+def ucld(A: CSR, line: int = 16) -> float:
+    """Useful cacheline density (csr_ucld, host)."""
+    rp, ci = _host_pattern(A)
+    out = ctypes.c_double()
+    check(_lib.load().csr_ucld(A.m, A.nnz, _ptr(rp), _ptr(ci), line, ctypes.byref(out)), "csr_ucld")
+    return out.value
+
+
 # ---------------------------------------------------------------- probes
 
 PROBE_KINDS = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "flush": 4}
