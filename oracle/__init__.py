@@ -210,6 +210,82 @@ def permute(A: CSR, perm) -> CSR:
     return csr_from_coo(A.m, A.n, inv[rows].astype(np.int32), inv[A.colind].astype(np.int32), A.values)
 
 
+@dataclass
+class BCSR:
+    """Register-blocked CRS (Sec. 4.5): A cut into a x b blocks; every block
+    holding a nonzero is kept.  Block rows ascend, block columns ascend inside
+    a block row.  Dense form: `values` holds a*b entries per block, row-major
+    inside the block, zeros explicit.  Bitmap form: `mask[q]` has bit
+    (r*b + c) set for each nonzero at (r, c) of block q, and `values` holds
+    only the nonzeros, block after block, in bit order (`offset[q]` = index
+    of block q's first value)."""
+    m: int
+    n: int
+    a: int
+    b: int
+    browptr: np.ndarray
+    bcol: np.ndarray
+    values: np.ndarray
+    mask: np.ndarray = None
+    offset: np.ndarray = None
+
+    @property
+    def nblocks(self) -> int:
+        return int(self.browptr[-1])
+
+
+def to_bcsr(A: CSR, a: int, b: int, bitmap: bool = False) -> BCSR:
+    """Block the matrix, from the definition: block (I, J) holds the entries
+    (I*a + r, J*b + c), 0 <= r < a, 0 <= c < b."""
+    mb = -(-A.m // a)
+    rows = A.row_of().astype(np.int64)
+    cols = A.colind.astype(np.int64)
+    key = (rows // a) * (-(-A.n // b) + 1) + cols // b
+    pos = (rows % a) * b + cols % b
+    order = np.lexsort((pos, key))  # blocks in (block row, block column) order, entries by position
+    key, pos, vals = key[order], pos[order], A.values[order]
+    uniq, first = np.unique(key, return_index=True)
+    nb = uniq.size
+    brow = uniq // (-(-A.n // b) + 1)
+    bcol = (uniq % (-(-A.n // b) + 1)).astype(np.int32)
+    browptr = np.searchsorted(brow, np.arange(mb + 1), side="left").astype(np.int32)
+    blk = np.repeat(np.arange(nb), np.diff(np.append(first, key.size)))
+    if not bitmap:
+        dense = np.zeros(nb * a * b, dtype=np.float64)
+        dense[blk * a * b + pos] = vals
+        return BCSR(A.m, A.n, a, b, browptr, bcol, dense)
+    mask = np.zeros(nb, dtype=np.uint64)
+    np.bitwise_or.at(mask, blk, np.left_shift(np.uint64(1), pos.astype(np.uint64)))
+    return BCSR(A.m, A.n, a, b, browptr, bcol, vals.copy(), mask, first.astype(np.int32))
+
+
+def bcsr_dense(B: BCSR) -> np.ndarray:
+    """The m x n matrix a BCSR holds (explicit zeros and padding dropped)."""
+    mb = B.browptr.size - 1
+    D = np.zeros((mb * B.a, (-(-B.n // B.b)) * B.b), dtype=np.float64)
+    for I in range(mb):
+        for q in range(B.browptr[I], B.browptr[I + 1]):
+            J = int(B.bcol[q])
+            if B.mask is None:
+                blk = B.values[q * B.a * B.b:(q + 1) * B.a * B.b].reshape(B.a, B.b)
+            else:
+                blk = np.zeros(B.a * B.b)
+                bits = [t for t in range(B.a * B.b) if (int(B.mask[q]) >> t) & 1]
+                blk[bits] = B.values[B.offset[q]:B.offset[q] + len(bits)]
+                blk = blk.reshape(B.a, B.b)
+            D[I * B.a:(I + 1) * B.a, J * B.b:(J + 1) * B.b] = blk
+    return D[:B.m, :B.n]
+
+
+def bcsr_bytes(B: BCSR) -> int:
+    """Bytes the blocked matrix occupies: values, one 4-byte column per block
+    and the block-row pointers (+ the 8-byte mask and 4-byte offset per block
+    in bitmap form).  A dense 8 x 8 block is 8*64 + 4 = 516 B (Sec. 4.5)."""
+    nb = B.nblocks
+    extra = 12 * nb if B.mask is not None else 0
+    return 8 * int(B.values.size if B.mask is None else B.values.size) + 4 * nb + 4 * B.browptr.size + extra
+
+
 def max_threads() -> int:
     return int(lib().orc_max_threads())
 

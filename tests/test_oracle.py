@@ -487,3 +487,44 @@ def test_vector_access_brute_force_and_closed_forms():
     F = oracle.csr_from_coo(64, 48, rr.ravel(), cc.ravel(), np.ones(rr.size))
     assert oracle.vector_access(F, 16, 8, 8) == 8.0
     assert oracle.vector_access(F, 16, 8, 64) == 1.0
+
+
+# ---------------------------------------------------------------- register blocking (Sec. 4.5)
+
+@pytest.mark.parametrize("a,b", [(1, 1), (8, 1), (1, 8), (2, 4), (8, 8), (4, 2), (3, 5)])
+def test_bcsr_roundtrip_and_block_count(a, b):
+    rng = np.random.default_rng(60 + a * 10 + b)
+    for m, n, nnz in [(1, 1, 1), (13, 29, 40), (70, 55, 600), (64, 64, 4096)]:
+        r, c, v = rand_coo(rng, m, n, nnz, dup=False)
+        A = oracle.csr_from_coo(m, n, r, c, v)
+        blocks = {(int(i) // a, int(j) // b) for i, j in zip(A.row_of(), A.colind)}
+        for bitmap in (False, True):
+            B = oracle.to_bcsr(A, a, b, bitmap)
+            assert B.nblocks == len(blocks)
+            assert np.array_equal(oracle.bcsr_dense(B), dense(A))
+            for I in range(B.browptr.size - 1):
+                cols = B.bcol[B.browptr[I]:B.browptr[I + 1]]
+                assert np.all(np.diff(cols) > 0)
+                assert {(I, int(J)) for J in cols} == {blk for blk in blocks if blk[0] == I}
+            if bitmap:
+                counts = np.array([bin(int(x)).count("1") for x in B.mask])
+                assert counts.sum() == A.nnz
+                assert np.array_equal(B.offset, np.concatenate([[0], np.cumsum(counts)[:-1]]))
+
+
+def test_bcsr_bytes_match_the_paper():
+    """A dense 8 x 8 region: 768 B in CRS (64 x 8 + 64 x 4) and 516 B blocked
+    (64 x 8 + one 4-byte offset), Sec. 4.5; blocking saves memory only above
+    (8ab + 4) / 12 nonzeros per block, 43 of 64 (67 %, the paper's "70 %")."""
+    rr, cc = np.meshgrid(np.arange(8, dtype=np.int32), np.arange(8, dtype=np.int32), indexing="ij")
+    A = oracle.csr_from_coo(8, 8, rr.ravel(), cc.ravel(), np.ones(64))
+    B = oracle.to_bcsr(A, 8, 8)
+    rowptr_bytes = 4 * B.browptr.size
+    assert oracle.bcsr_bytes(B) - rowptr_bytes == 516
+    assert 12 * A.nnz == 768
+    rng = np.random.default_rng(61)
+    for t, relation in [(42, -1), (43, 0), (44, 1)]:
+        pick = rng.choice(64, t, replace=False)
+        S = oracle.csr_from_coo(8, 8, rr.ravel()[pick], cc.ravel()[pick], np.ones(t))
+        blocked = oracle.bcsr_bytes(oracle.to_bcsr(S, 8, 8)) - rowptr_bytes
+        assert np.sign(12 * t - blocked) == relation, t
