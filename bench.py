@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the unflushed (warm) calls, so a kernel trace holds flushed calls only")
     ap.add_argument("--forms", default="c0,c2,c3,c4",
-                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep; rcm = RCM ordering)")
+                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep; rcm = RCM ordering; bcsr = register blocking)")
     ap.add_argument("--form-steps", type=int, default=20)
     return ap.parse_args()
 
@@ -373,6 +373,42 @@ def bench_rcm(ctx, A1=None):
     return out
 
 
+# ---------------------------------------------------------------- register blocking (Sec. 4.5)
+
+def bench_bcsr(ctx, A1=None):
+    """SpMV on register-blocked CRS against the CSR kernel (the paper's
+    relative-performance table, Sec. 4.5): dense a x b blocks with explicit
+    zeros, and bitmap blocks (64-bit mask + packed nonzeros).  FP64, flushed.
+    Density = nonzeros / stored values."""
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    out = {}
+    mats = [("stencil27_128", upload(torch, spx, spgen.workload_c2_stencil(0), dev),
+             [(8, 8), (8, 4), (8, 2), (8, 1), (4, 8), (2, 8), (1, 8), (4, 4), (2, 2)])]
+    if A1 is not None:  # sparse rows: blocks above 8 values would mostly store zeros
+        mats.append(("powerlaw_1M", A1, [(8, 1), (4, 1), (2, 1), (1, 8), (1, 4), (2, 2)]))
+    for name, A, shapes in mats:
+        m, n, nnz = A.m, A.n, A.nnz
+        x = torch.from_numpy(spgen.uniform(n, 14, spgen.TAG_X)).to(dev)
+        y = torch.empty(m, dtype=torch.float64, device=dev)
+        plan = spx.Plan.for_matrix(A, spx.default_opts(1))
+        t_csr = float(ctx["timer"].run([lambda: spx.spmv(A, x, y=y, plan=plan)], ctx["fsteps"], 3)[:, 0].mean())
+        ref = y.clone()
+        rows = {"csr": {"us": t_csr * 1e6, "gflops": 2 * nnz / t_csr / 1e9, "bytes": 12 * nnz + 4 * (m + 1)}}
+        variants = [(a, b, False) for a, b in shapes] + [(8, 8, True), (8, 1, True), (4, 4, True), (1, 8, True)]
+        for a, b, bitmap in variants:
+            B = spx.BCSR.from_csr(A, a, b, bitmap)
+            t = float(ctx["timer"].run([lambda: spx.bcsr_spmv(B, x, y=y)], ctx["fsteps"], 3)[:, 0].mean())
+            err = float((y - ref).abs().max() / ref.abs().max())
+            rows[f"{a}x{b}{'_bitmap' if bitmap else ''}"] = {
+                "us": t * 1e6, "gflops": 2 * nnz / t / 1e9, "relative_to_csr": t_csr / t,
+                "density": nnz / (B.nblocks * a * b) if B.nblocks else 0.0, "blocks": B.nblocks,
+                "bytes": B.stored_bytes(), "max_rel_diff_vs_csr": err}
+            del B
+            torch.cuda.empty_cache()
+        out[name] = rows
+    return out
+
+
 # ---------------------------------------------------------------- c3
 
 def bench_c3(ctx):
@@ -581,6 +617,8 @@ def main():
                     forms[name] = bench_occupancy(ctx, A)
                 elif name == "rcm":
                     forms[name] = bench_rcm(ctx, A)
+                elif name == "bcsr":
+                    forms[name] = bench_bcsr(ctx, A)
                 forms[name]["bench_s"] = round(time.time() - f0, 1)
             except Exception as e:  # a failing form is reported, not hidden
                 forms[name] = {"error": repr(e)}

@@ -266,6 +266,38 @@ spx_status csr_vector_access(int32_t m, int32_t n, int32_t nnz, const int32_t *h
 spx_status csr_ucld(int32_t m, int32_t nnz, const int32_t *host_rowptr, const int32_t *host_colind,
                     int32_t line, double *out);
 
+/* ---------------------------------------------------------------- register blocking
+ * Register-blocked CRS (Sec. 4.5): A is cut into a x b blocks (a, b in
+ * {1, 2, 4, 8}); every block that holds a nonzero is kept, block rows
+ * ascending and block columns ascending inside a block row.  browptr
+ * int32[ceil(m/a)+1] and bcol int32[nblocks] index the blocks.  Dense form
+ * (bitmap = 0): bvals f64[nblocks*a*b], row-major inside each block, zeros
+ * explicit (the paper's register blocking).  Bitmap form (bitmap = 1): bmask
+ * uint64[nblocks] has bit r*b+c set for a nonzero at (r, c) of the block;
+ * bvals f64[nnz] holds the nonzeros block after block in bit order and
+ * boff int32[nblocks] the index of each block's first value (the sparse block
+ * storage the paper proposes as its next step).  The input CSR must have
+ * ascending columns inside rows (csr_from_coo's output does).
+ * csr_bcsr_count writes the block count to *nblocks_out (device int32) so the
+ * caller can size the outputs; csr_to_bcsr then fills them.  Both use the
+ * workspace of bcsr_workspace_bytes and run asynchronously on `stream`. */
+spx_status bcsr_workspace_bytes(int32_t m, int32_t n, int32_t nnz, size_t *bytes);
+spx_status csr_bcsr_count(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                          int32_t a, int32_t b, int32_t *nblocks_out, void *workspace, size_t ws_bytes,
+                          void *stream);
+spx_status csr_to_bcsr(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                       const double *values, int32_t a, int32_t b, int32_t bitmap, int32_t *browptr,
+                       int32_t *bcol, double *bvals, uint64_t *bmask, int32_t *boff, void *workspace,
+                       size_t ws_bytes, void *stream);
+
+/* y <- A x with A in register-blocked form (Sec. 4.5), FP64.  Each block row
+ * is served by `lanes` threads (a power of two <= 64; 0 picks it from the
+ * mean blocks per block row); every thread multiplies whole blocks and the
+ * group reduces its a partial sums.  x f64[n], y f64[m] (overwritten). */
+spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int32_t bitmap, int32_t nblocks,
+                     const int32_t *browptr, const int32_t *bcol, const double *bvals, const uint64_t *bmask,
+                     const int32_t *boff, const double *x, double *y, int32_t lanes, void *stream);
+
 /* ---------------------------------------------------------------- probes
  * Memory-system probes (the GPU counterparts of the paper's read / write
  * bandwidth microbenchmarks, Sec. 2.1 and 2.2), used to calibrate measured

@@ -347,6 +347,75 @@ def ucld(A: CSR, line: int = 16) -> float:
     return out.value
 
 
+# ---------------------------------------------------------------- register blocking
+
+@dataclass
+class BCSR:
+    """Register-blocked matrix on the device (see csr_to_bcsr in include/spx.h)."""
+    m: int
+    n: int
+    a: int
+    b: int
+    bitmap: bool
+    browptr: torch.Tensor
+    bcol: torch.Tensor
+    bvals: torch.Tensor
+    bmask: torch.Tensor | None
+    boff: torch.Tensor | None
+
+    @property
+    def nblocks(self) -> int:
+        return int(self.bcol.numel()) if self.bcol is not None else 0
+
+    @staticmethod
+    def from_csr(A: CSR, a: int, b: int, bitmap: bool = False) -> "BCSR":
+        L = _lib.load()
+        _dev(A.rowptr, A.colind, A.values)
+        if A.values.dtype != torch.float64:
+            raise TypeError("register blocking takes FP64 values")
+        nb = ctypes.c_size_t()
+        check(L.bcsr_workspace_bytes(A.m, A.n, A.nnz, ctypes.byref(nb)), "bcsr_workspace_bytes")
+        ws = _workspace(nb.value, A.device)
+        cnt = torch.empty(1, dtype=torch.int32, device=A.device)
+        check(L.csr_bcsr_count(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), a, b, _ptr(cnt), _ptr(ws),
+                               nb.value, _stream()), "csr_bcsr_count")
+        nblocks = int(cnt.item())
+        dev = A.device
+        mb = -(-A.m // a)
+        browptr = torch.empty(mb + 1, dtype=torch.int32, device=dev)
+        bcol = torch.empty(max(nblocks, 1), dtype=torch.int32, device=dev)
+        bvals = torch.empty(max(A.nnz if bitmap else nblocks * a * b, 1), dtype=torch.float64, device=dev)
+        bmask = torch.empty(max(nblocks, 1), dtype=torch.int64, device=dev) if bitmap else None
+        boff = torch.empty(max(nblocks, 1), dtype=torch.int32, device=dev) if bitmap else None
+        check(L.csr_to_bcsr(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(A.values), a, b, int(bitmap),
+                            _ptr(browptr), _ptr(bcol), _ptr(bvals), _ptr(bmask), _ptr(boff), _ptr(ws), nb.value,
+                            _stream()), "csr_to_bcsr")
+        keep = nblocks
+        return BCSR(A.m, A.n, a, b, bitmap, browptr, bcol[:keep],
+                    bvals[:A.nnz] if bitmap else bvals[:nblocks * a * b],
+                    bmask[:keep] if bitmap else None, boff[:keep] if bitmap else None)
+
+    def stored_bytes(self) -> int:
+        """Values, one column index per block, block-row pointers (+ mask and
+        offset per block in bitmap form)."""
+        extra = 12 * self.nblocks if self.bitmap else 0
+        return 8 * int(self.bvals.numel()) + 4 * self.nblocks + 4 * int(self.browptr.numel()) + extra
+
+
+def bcsr_spmv(B: BCSR, x: torch.Tensor, y: torch.Tensor | None = None, lanes: int = 0) -> torch.Tensor:
+    """y <- A x for a register-blocked A (bcsr_spmv), FP64."""
+    _dev(x)
+    _contig(x)
+    if x.dtype != torch.float64 or x.numel() != B.n:
+        raise ValueError("x must be float64 with n entries")
+    if y is None:
+        y = torch.empty(B.m, dtype=torch.float64, device=x.device)
+    check(_lib.load().bcsr_spmv(B.m, B.n, B.a, B.b, int(B.bitmap), B.nblocks, _ptr(B.browptr), _ptr(B.bcol),
+                                _ptr(B.bvals), _ptr(B.bmask), _ptr(B.boff), _ptr(x), _ptr(y), lanes, _stream()),
+          "bcsr_spmv")
+    return y
+
+
 # ---------------------------------------------------------------- probes
 
 PROBE_KINDS = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "flush": 4}
