@@ -571,6 +571,21 @@ def main():
               "setup_s": round(setup_s, 2), "wall_s_timed_incl_flush": round(wall, 4),
               "source_hash": source_hash()}
 
+    # random-access ceilings of the two gathers, on buffers the size of X and x
+    gather = {}
+    for kind, nbytes, per_round, label in (("gather_rows", n * k * 8, 8, "X_rows_128B"),
+                                           ("gather_elems", n * 8, 64, "x_elems_8B")):
+        buf = torch.zeros(nbytes // 8, dtype=torch.float64, device=dev)
+        blocks = 4096
+        fn = lambda buf=buf, kind=kind: spx.probe(kind, buf, None, blocks)  # noqa: E731
+        tg = float(np.median(Timer(torch, dev, False).run([fn], 5, 2)[:, 0]))
+        rate = blocks * 4 * spx.ops.GATHER_ROUNDS * per_round / tg
+        gather[label] = {"buffer_bytes": nbytes, "g_accesses_per_s": rate / 1e9}
+        del buf
+    gather["spmm_x_rows_g_per_s"] = nnz / float(tm.mean()) / 1e9
+    gather["spmv_x_elems_g_per_s"] = nnz / float(tv.mean()) / 1e9
+    detail["gather_ceiling"] = gather
+
     cpu = None
     if not args.no_cpu:
         import oracle

@@ -304,8 +304,14 @@ spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int32_t bitmap,
  * bandwidth.  kind 0: streaming read of buf (buf2: optional device double
  * that keeps the loads live); 1: write buf; 2: non-temporal write of buf;
  * 3: non-temporal copy buf -> buf2; 4: read-modify-write of buf (a cache
- * flush).  bytes is rounded down to 16-byte units; buffers must be 16-byte
- * aligned; blocks <= 0 picks 4096 workgroups of 256 threads. */
+ * flush); 5: random gather of 128-byte rows of buf (8 lanes x 16 bytes per
+ * row, the SpMM X access at k = 16 FP64); 6: random gather of 8-byte
+ * elements of buf (the SpMV x access).  Kinds 5 and 6 make 256 rounds per
+ * wavefront (4 wavefronts per workgroup); a round reads 8 rows (kind 5) or
+ * 64 elements (kind 6); they give the random-access ceiling of a working set
+ * of `bytes` (Sec. 4.2's latency argument).  bytes is rounded down to
+ * 16-byte units; buffers must be 16-byte aligned; blocks <= 0 picks 4096
+ * workgroups of 256 threads. */
 spx_status spx_probe(int32_t kind, void *buf, void *buf2, size_t bytes, int32_t blocks, void *stream);
 
 #ifdef __cplusplus

@@ -39,6 +39,7 @@ void layout_for_k(int32_t k, spx_dtype xt, const void* X, int64_t ldx, const voi
   const bool vec_ok = !(flags & SPX_FLAG_SCALAR_X) && (k % V == 0) && (ldx % V == 0) &&
                       (ldy % V == 0) && aligned16_(X) && aligned16_(Y);
   *vec = vec_ok ? V : 1;
+
   const int per = (k + *vec - 1) / *vec;
   int l = 1;
   while (l < per && l < 32) l <<= 1;

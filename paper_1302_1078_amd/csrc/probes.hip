@@ -48,13 +48,54 @@ __global__ __launch_bounds__(kWG) void k_probe_flush(d2* __restrict__ p, int64_t
     p[i] = p[i] + 1.0;
 }
 
+// Random gathers: the access pattern of the products' x / X reads, without
+// the matrix stream.  Every wave makes kGatherIters rounds; a round of
+// kind 5 reads 8 random 128-byte rows (8 lanes x 16 bytes each, the SpMM
+// layout for k = 16 FP64), a round of kind 6 reads 64 random 8-byte
+// elements (the SpMV x gather).  Four rounds are in flight per lane.
+constexpr int kGatherIters = 256;
+
+__device__ __forceinline__ uint32_t scramble(uint32_t v) {  // an integer hash (xorshift-multiply)
+  v ^= v >> 16;
+  v *= 0x7feb352dU;
+  v ^= v >> 15;
+  v *= 0x846ca68bU;
+  v ^= v >> 16;
+  return v;
+}
+
+template <bool ROWS>
+__global__ __launch_bounds__(kWG) void k_probe_gather(const double* __restrict__ p, int64_t n, double* out) {
+  const int lane = threadIdx.x % kWave;
+  const uint32_t wave = blockIdx.x * (kWG / kWave) + threadIdx.x / kWave;
+  const int64_t rows = n / 16;  // 128-byte rows
+  double acc = 0.0;
+  for (int it = 0; it < kGatherIters; it += 4) {
+    d2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t h = scramble(wave * 977u + static_cast<uint32_t>(it + u) * 131u);
+      if (ROWS) {
+        const int64_t r = scramble(h + lane / 8) % rows;
+        v[u] = *reinterpret_cast<const d2*>(p + r * 16 + (lane % 8) * 2);
+      } else {
+        v[u] = d2{p[scramble(h + lane) % n], 0.0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += v[u][0] + v[u][1];
+  }
+  if (out && acc == 12345.678) out[0] = acc;
+}
+
 }  // namespace
 }  // namespace spx
 
 using namespace spx;
 
 // kind: 0 read, 1 write, 2 write non-temporal, 3 copy (src = buf, dst = buf2),
-// 4 flush (read-modify-write).  bytes is rounded down to 16-byte units.
+// 4 flush (read-modify-write), 5 random 128-byte row gather, 6 random 8-byte
+// gather.  bytes is rounded down to 16-byte units.
 extern "C" spx_status spx_probe(int32_t kind, void* buf, void* buf2, size_t bytes, int32_t blocks,
                                 void* stream) {
   if (!buf || bytes < 16) return fail(SPX_ERR_INVALID, "spx_probe: empty buffer");
@@ -71,6 +112,14 @@ extern "C" spx_status spx_probe(int32_t kind, void* buf, void* buf2, size_t byte
     case 2: k_probe_write<<<g, kWG, 0, st>>>(p, n, 1, 1.0); break;
     case 3: k_probe_copy<<<g, kWG, 0, st>>>(p, static_cast<d2*>(buf2), n); break;
     case 4: k_probe_flush<<<g, kWG, 0, st>>>(p, n); break;
+    case 5:
+    case 6: {
+      const int64_t elems = static_cast<int64_t>(bytes / 8);
+      if ((kind == 5 && elems < 16) || elems < 1) return fail(SPX_ERR_INVALID, "spx_probe: gather buffer too small");
+      if (kind == 5) k_probe_gather<true><<<g, kWG, 0, st>>>(static_cast<const double*>(buf), elems, static_cast<double*>(buf2));
+      else k_probe_gather<false><<<g, kWG, 0, st>>>(static_cast<const double*>(buf), elems, static_cast<double*>(buf2));
+      break;
+    }
     default: return fail(SPX_ERR_INVALID, "spx_probe: kind=%d", kind);
   }
   SPX_LAUNCHED("spx_probe");

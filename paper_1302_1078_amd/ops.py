@@ -418,7 +418,9 @@ def bcsr_spmv(B: BCSR, x: torch.Tensor, y: torch.Tensor | None = None, lanes: in
 
 # ---------------------------------------------------------------- probes
 
-PROBE_KINDS = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "flush": 4}
+PROBE_KINDS = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "flush": 4, "gather_rows": 5,
+               "gather_elems": 6}
+GATHER_ROUNDS = 256  # rounds per wavefront of the gather probes
 
 
 def probe(kind: str, buf: torch.Tensor, buf2: torch.Tensor | None = None, blocks: int = 0) -> None:

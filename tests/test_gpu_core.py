@@ -338,3 +338,24 @@ def test_occupancy_cap_same_result(spx, torch, k):
     assert all(np.array_equal(outs[0], y) for y in outs[1:])
     ref = oracle.spmm(A, X) if k > 1 else oracle.spmv(A, X[:, 0])
     assert oracle.rel2(outs[0].view(np.float64).ravel(), ref.ravel()) <= TOL_F64
+
+
+def test_memory_probes_run_and_keep_data(spx, torch):
+    """Every probe kind launches and finishes; the read-only kinds leave the
+    buffer unchanged, write / copy / flush change it as documented."""
+    a = torch.arange(1 << 16, dtype=torch.float64, device="cuda:0")
+    keep = a.clone()
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    for kind in ("read", "gather_rows", "gather_elems"):
+        spx.probe(kind, a, sink, 64)
+    torch.cuda.synchronize()
+    assert torch.equal(a, keep)
+    b = torch.empty_like(a)
+    spx.probe("copy", a, b, 64)
+    assert torch.equal(a, b)
+    spx.probe("flush", b, None, 64)
+    assert torch.equal(b, a + 1.0)
+    spx.probe("write", b, None, 64)
+    assert torch.equal(b, torch.ones_like(b))
+    with pytest.raises(spx.SpxError):
+        spx.probe("gather_rows", a[:8], None, 64)
