@@ -40,20 +40,35 @@ template <typename VT>
 struct ValueLoad;
 template <>
 struct ValueLoad<double> {
+  using Raw = double;
   template <bool NT = true>
   static __device__ __forceinline__ double get(const double* p) { return ld_mat<NT>(p); }
+  template <bool NT = true>
+  static __device__ __forceinline__ Raw raw(const double* p) { return ld_mat<NT>(p); }
+  static __device__ __forceinline__ double widen(Raw r) { return r; }
 };
 template <>
 struct ValueLoad<float> {
+  using Raw = float;
   template <bool NT = true>
   static __device__ __forceinline__ float get(const float* p) { return ld_mat<NT>(p); }
+  template <bool NT = true>
+  static __device__ __forceinline__ Raw raw(const float* p) { return ld_mat<NT>(p); }
+  static __device__ __forceinline__ float widen(Raw r) { return r; }
 };
+// BF16: raw() keeps the stored bits so that a caller can defer the widening
+// until the value is used (widening right after a masked load makes the
+// compiler wait for that load on the spot).
 template <>
 struct ValueLoad<uint16_t> {
+  using Raw = uint16_t;
   template <bool NT = true>
   static __device__ __forceinline__ float get(const uint16_t* p) {
     return bf16_to_f32(ld_mat<NT>(p));
   }
+  template <bool NT = true>
+  static __device__ __forceinline__ Raw raw(const uint16_t* p) { return ld_mat<NT>(p); }
+  static __device__ __forceinline__ float widen(Raw r) { return bf16_to_f32(r); }
 };
 
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }

@@ -411,11 +411,16 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   // s_off[r] <= j, found by a fixed 8-step branchless search run for all
   // kStreamPer elements in lockstep (the LDS reads of a step are independent,
   // so a lane waits for 8 LDS round trips per chunk, not 8 per element).
-  auto fetch = [&](int32_t base, int32_t (&cc)[kStreamPer], XT (&vv)[kStreamPer]) {
+  // Slots past the tile's last element load that element again instead of
+  // branching around the loads (a masked load followed by a use makes the
+  // compiler wait for it at once); their products are never summed.
+  using VL = ValueLoad<typename C::VT>;
+  using Raw = typename VL::Raw;
+  auto fetch = [&](int32_t base, int32_t (&cc)[kStreamPer], Raw (&vv)[kStreamPer]) {
     int32_t jj[kStreamPer], lo[kStreamPer];
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u) {
-      jj[u] = base + u * kWG + t;
+      jj[u] = min(base + u * kWG + t, total - 1);
       lo[u] = 0;
     }
 #pragma unroll
@@ -427,27 +432,27 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u) {
       const int32_t p = s_p0[lo[u]] + (jj[u] - s_off[lo[u]]);
-      const bool h = jj[u] < total;
-      cc[u] = h ? ld_mat<C::kNT>(a.colind + p) : 0;
-      vv[u] = h ? value_at<C>(a, p) : XT(0);
+      cc[u] = ld_mat<C::kNT>(a.colind + p);
+      const int32_t q = a.vperm ? ld_mat<C::kNT>(a.vperm + p) : p;
+      vv[u] = VL::template raw<C::kNT>(static_cast<const typename C::VT*>(a.values) + q);
     }
   };
   // software pipeline: the next chunk's colind / values are in flight while
   // the current chunk gathers x and reduces through LDS
   int32_t cA[kStreamPer];
-  XT vA[kStreamPer];
-  fetch(0, cA, vA);
+  Raw vA[kStreamPer];
+  if (total > 0) fetch(0, cA, vA);
   for (int32_t base = 0; base < total; base += kStreamChunk) {
     const bool more = base + kStreamChunk < total;
     int32_t cB[kStreamPer];
-    XT vB[kStreamPer];
+    Raw vB[kStreamPer];
     if (more) fetch(base + kStreamChunk, cB, vB);
     XT xv[kStreamPer];
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u)
       xv[u] = (base + u * kWG + t < total) ? X[static_cast<int64_t>(cA[u]) * a.ldx] : XT(0);
 #pragma unroll
-    for (int u = 0; u < kStreamPer; ++u) s_prod[u * kWG + t] = vA[u] * xv[u];
+    for (int u = 0; u < kStreamPer; ++u) s_prod[u * kWG + t] = static_cast<XT>(VL::widen(vA[u])) * xv[u];
     __syncthreads();
     const int32_t b0 = max(off, base) - base;
     const int32_t b1 = min(off + L, base + kStreamChunk) - base;
