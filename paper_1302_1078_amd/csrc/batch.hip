@@ -1,15 +1,19 @@
-// batch.hip -- many independent products Y_b <- A_b X_b in one persistent
-// launch (the paper's motivation: many SpMV/SpMM-based requests served at
+// batch.hip -- many independent products Y_b <- A_b X_b in a few persistent
+// launches (the paper's motivation: many SpMV/SpMM-based requests served at
 // once, Sec. 1 and Sec. 5).
 //
 // At creation every matrix is binned with its own plan options (from an
-// autotuner or the defaults) and its row-group tiles are appended to one
-// global tile list, ordered by estimated cost (heaviest first).  At run time
-// a reset kernel zeroes the queue head and a persistent kernel (one grid of
-// CUs x 8 workgroups) pops tiles with an atomic counter until the list is
-// empty.  Each tile runs exactly the row-group code of the single-matrix
-// launch with the matrix's own arguments, so every result is bit-identical to
-// csr_spmv / csr_spmm with the same plan options.
+// autotuner or the defaults) and its row-group tiles are appended to a tile
+// list grouped by lane layout (the (KL, VEC) that its k selects) and, inside
+// a group, ordered by estimated cost (heaviest first).  At run time a reset
+// kernel zeroes the queue heads and one persistent kernel per layout present
+// (a grid of up to CUs x 8 workgroups) pops its group's tiles with an atomic
+// counter until they are gone.  A kernel per layout keeps each launch's
+// register use, and so its occupancy, that of the single-matrix kernel of the
+// same layout (one kernel holding every layout needed over 220 VGPRs, two
+// waves per SIMD).  Each tile runs exactly the row-group code of the
+// single-matrix launch with the matrix's own arguments, so every result is
+// bit-identical to csr_spmv / csr_spmm with the same plan options.
 #include <string.h>
 
 #include <algorithm>
@@ -41,8 +45,9 @@ struct BatchArgs {
 // layouts: 0 -> (KL 1, VEC 1); i >= 1 -> (KL 2^(i-1), VEC V)
 constexpr int kLayouts = 7;
 
-template <class C>
+template <class C, bool MR>
 __device__ __forceinline__ void run_tile(const ProdArgs& a, const BinDesc& d, int tile) {
+  constexpr bool kMulti = MR && C::KL == 1 && C::VEC == 1;
   switch (d.lanes + (d.rpg > 1 ? 1000 : 0)) {
     case 1: do_rows<C, 1, 1>(a, d, tile); break;
     case 2: do_rows<C, 2, 1>(a, d, tile); break;
@@ -53,27 +58,27 @@ __device__ __forceinline__ void run_tile(const ProdArgs& a, const BinDesc& d, in
     case 64: do_rows<C, 64, 1>(a, d, tile); break;
     case 256: do_rows<C, 256, 1>(a, d, tile); break;
     case 1001:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 1, 4>(a, d, tile);
+      if constexpr (kMulti) do_rows<C, 1, 4>(a, d, tile);
       else do_rows<C, 1, 1>(a, d, tile);
       break;
     case 1002:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 2, 4>(a, d, tile);
+      if constexpr (kMulti) do_rows<C, 2, 4>(a, d, tile);
       else do_rows<C, 2, 1>(a, d, tile);
       break;
     case 1004:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 4, 4>(a, d, tile);
+      if constexpr (kMulti) do_rows<C, 4, 4>(a, d, tile);
       else do_rows<C, 4, 1>(a, d, tile);
       break;
     case 1008:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 8, 4>(a, d, tile);
+      if constexpr (kMulti) do_rows<C, 8, 4>(a, d, tile);
       else do_rows<C, 8, 1>(a, d, tile);
       break;
     case 1016:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 16, 4>(a, d, tile);
+      if constexpr (kMulti) do_rows<C, 16, 4>(a, d, tile);
       else do_rows<C, 16, 1>(a, d, tile);
       break;
     case 1032:
-      if constexpr (C::KL == 1 && C::VEC == 1) do_rows<C, 32, 4>(a, d, tile);
+      if constexpr (kMulti) do_rows<C, 32, 4>(a, d, tile);
       else do_rows<C, 32, 1>(a, d, tile);
       break;
     case SPX_LANES_STREAM:
@@ -84,7 +89,9 @@ __device__ __forceinline__ void run_tile(const ProdArgs& a, const BinDesc& d, in
   }
 }
 
-__global__ void k_batch_reset(int32_t* head) { *head = 0; }
+__global__ void k_batch_reset(int32_t* heads, int n) {
+  if (static_cast<int>(threadIdx.x) < n) heads[threadIdx.x] = 0;
+}
 
 // The loop must stay uniform: its header is a barrier (a convergent operation
 // the compiler cannot duplicate), and every value that steers control flow is
@@ -98,7 +105,11 @@ __global__ void k_batch_reset(int32_t* head) { *head = 0; }
 // the launch on one address.
 constexpr int kPop = 16;
 
-template <typename VT, typename XT, int V>
+// One persistent launch per lane layout: each instantiation holds only the
+// code of its layout, so its register use (and occupancy) is that of the
+// single-matrix kernel of the same layout.  MR adds the multi-row path of
+// short-row SpMV bins, as in the single-matrix launch.
+template <class C, bool MR>
 __global__ __launch_bounds__(kWG) void k_batch(const BatchArgs b) {
   __shared__ int32_t next;
   int32_t id = 0, end = 0;
@@ -116,7 +127,6 @@ __global__ __launch_bounds__(kWG) void k_batch(const BatchArgs b) {
     ++id;
     const int32_t mat = __builtin_amdgcn_readfirstlane(tp->mat);
     const int32_t slot = __builtin_amdgcn_readfirstlane(tp->slot);
-    const int32_t layout = __builtin_amdgcn_readfirstlane(tp->layout);
     const int32_t tile = __builtin_amdgcn_readfirstlane(tp->tile);
     const ProdArgs& a = b.mats[mat];
     BinDesc d;
@@ -127,16 +137,7 @@ __global__ __launch_bounds__(kWG) void k_batch(const BatchArgs b) {
     d.lanes = __builtin_amdgcn_readfirstlane(a.bins[slot].lanes);
     d.bin = 0;
     d.rpg = __builtin_amdgcn_readfirstlane(a.bins[slot].rpg);
-    const TileDesc td{mat, static_cast<int16_t>(slot), static_cast<int16_t>(layout), tile};
-    switch (td.layout) {
-      case 0: run_tile<Cfg<VT, XT, 1, 1>>(a, d, td.tile); break;
-      case 1: run_tile<Cfg<VT, XT, 1, V>>(a, d, td.tile); break;
-      case 2: run_tile<Cfg<VT, XT, 2, V>>(a, d, td.tile); break;
-      case 3: run_tile<Cfg<VT, XT, 4, V>>(a, d, td.tile); break;
-      case 4: run_tile<Cfg<VT, XT, 8, V>>(a, d, td.tile); break;
-      case 5: run_tile<Cfg<VT, XT, 16, V>>(a, d, td.tile); break;
-      default: run_tile<Cfg<VT, XT, 32, V>>(a, d, td.tile); break;
-    }
+    run_tile<C, MR>(a, d, tile);
   }
 }
 
@@ -195,7 +196,7 @@ spx_status layout_ws(int32_t count, const spx_csr_desc* descs, BatchLayout* L) {
   L->tiles_off = off;
   off = align_up(off + sizeof(TileDesc) * static_cast<size_t>(L->max_tiles + 1));
   L->head_off = off;
-  off = align_up(off + sizeof(int32_t));
+  off = align_up(off + sizeof(int32_t) * kLayouts);
   L->total = off;
   return SPX_OK;
 }
@@ -219,11 +220,15 @@ struct spx_batch {
   spx_dtype vt, xt;
   int32_t count;
   int32_t ntiles;
-  int32_t grid;
+  int32_t grid;  // workgroups of the largest per-layout launch
   int64_t nseg;
-  int32_t* head;
+  int32_t* head;  // one queue head per layout
   spx::ProdArgs* mats;
   spx::TileDesc* tiles;
+  int32_t first[spx::kLayouts];  // tiles of layout l: [first[l], first[l] + ntile[l])
+  int32_t ntile[spx::kLayouts];
+  int32_t lgrid[spx::kLayouts];
+  bool multi_row;  // layout 0 has short-row bins served several rows per group
   std::vector<spx_plan*> plans;
 };
 
@@ -260,6 +265,7 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
 
   spx_batch* B = new (std::nothrow) spx_batch();
   if (!B) return fail(SPX_ERR_INVALID, "csr_batch_create: out of host memory");
+  B->multi_row = false;
   B->vt = vt;
   B->xt = xt;
   B->count = count;
@@ -303,6 +309,7 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
     bins_from_plan(p, a, kl);
     for (int j = 0; j < a.nbins; ++j) {
       const BinDesc& bd = a.bins[j];
+      if (lid == 0 && bd.rpg > 1) B->multi_row = true;
       double per_tile;
       if (bd.lanes == 0) {
         per_tile = o.split_chunk;
@@ -327,8 +334,10 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
       }
     }
   }
-  std::stable_sort(entries.begin(), entries.end(),
-                   [](const Entry& x, const Entry& y) { return x.cost > y.cost; });
+  // tiles grouped by layout (one launch each), heaviest first inside a group
+  std::stable_sort(entries.begin(), entries.end(), [](const Entry& x, const Entry& y) {
+    return x.td.layout != y.td.layout ? x.td.layout < y.td.layout : x.cost > y.cost;
+  });
   if (static_cast<int64_t>(entries.size()) > L.max_tiles || entries.size() > 0x7fffffffu)
     return cleanup(fail(SPX_ERR_INVALID, "csr_batch_create: tile list overflow"));
   std::vector<TileDesc> tiles(entries.size());
@@ -344,7 +353,19 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
       cus = v;
   }
   const int64_t want = static_cast<int64_t>(cus) * 8;
-  B->grid = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(want, B->ntiles)));
+  B->grid = 0;
+  for (int l = 0; l < kLayouts; ++l) {
+    B->first[l] = 0;
+    B->ntile[l] = 0;
+  }
+  for (size_t t = 0; t < tiles.size(); ++t) {
+    const int l = tiles[t].layout;
+    if (B->ntile[l]++ == 0) B->first[l] = static_cast<int32_t>(t);
+  }
+  for (int l = 0; l < kLayouts; ++l) {
+    B->lgrid[l] = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(want, B->ntile[l])));
+    if (B->ntile[l] > 0) B->grid = std::max(B->grid, B->lgrid[l]);
+  }
   hipError_t e = hipMemcpyAsync(B->mats, mats.data(), sizeof(ProdArgs) * count, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpyAsync(B->tiles, tiles.data(), sizeof(TileDesc) * tiles.size(), hipMemcpyHostToDevice, st);
@@ -354,18 +375,46 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
   return SPX_OK;
 }
 
+namespace spx {
+namespace {
+
+template <typename VT, typename XT, int V>
+spx_status launch_layout(const spx_batch* B, int l, hipStream_t st) {
+  const BatchArgs a{B->mats, B->tiles + B->first[l], B->ntile[l], B->head + l};
+  const unsigned g = static_cast<unsigned>(B->lgrid[l]);
+  switch (l) {
+    case 0:
+      if (B->multi_row) k_batch<Cfg<VT, XT, 1, 1>, true><<<g, kWG, 0, st>>>(a);
+      else k_batch<Cfg<VT, XT, 1, 1>, false><<<g, kWG, 0, st>>>(a);
+      break;
+    case 1: k_batch<Cfg<VT, XT, 1, V>, false><<<g, kWG, 0, st>>>(a); break;
+    case 2: k_batch<Cfg<VT, XT, 2, V>, false><<<g, kWG, 0, st>>>(a); break;
+    case 3: k_batch<Cfg<VT, XT, 4, V>, false><<<g, kWG, 0, st>>>(a); break;
+    case 4: k_batch<Cfg<VT, XT, 8, V>, false><<<g, kWG, 0, st>>>(a); break;
+    case 5: k_batch<Cfg<VT, XT, 16, V>, false><<<g, kWG, 0, st>>>(a); break;
+    default: k_batch<Cfg<VT, XT, 32, V>, false><<<g, kWG, 0, st>>>(a); break;
+  }
+  SPX_LAUNCHED("k_batch");
+  return SPX_OK;
+}
+
+}  // namespace
+}  // namespace spx
+
 extern "C" spx_status csr_batch_run(const spx_batch* B, void* stream) {
   if (!B) return fail(SPX_ERR_INVALID, "csr_batch_run: batch is null");
   if (B->ntiles == 0) return SPX_OK;
   hipStream_t st = as_stream(stream);
-  k_batch_reset<<<1, 1, 0, st>>>(B->head);
+  k_batch_reset<<<1, 64, 0, st>>>(B->head, kLayouts);
   SPX_LAUNCHED("k_batch_reset");
-  BatchArgs a{B->mats, B->tiles, B->ntiles, B->head};
-  const unsigned g = static_cast<unsigned>(B->grid);
-  if (B->vt == SPX_F64) k_batch<double, double, 2><<<g, kWG, 0, st>>>(a);
-  else if (B->vt == SPX_F32) k_batch<float, float, 4><<<g, kWG, 0, st>>>(a);
-  else k_batch<uint16_t, float, 4><<<g, kWG, 0, st>>>(a);
-  SPX_LAUNCHED("k_batch");
+  for (int l = 0; l < kLayouts; ++l) {
+    if (B->ntile[l] == 0) continue;
+    spx_status s;
+    if (B->vt == SPX_F64) s = launch_layout<double, double, 2>(B, l, st);
+    else if (B->vt == SPX_F32) s = launch_layout<float, float, 4>(B, l, st);
+    else s = launch_layout<uint16_t, float, 4>(B, l, st);
+    if (s != SPX_OK) return s;
+  }
   return SPX_OK;
 }
 
