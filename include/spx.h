@@ -195,13 +195,15 @@ spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, c
                      spx_dtype dtype, const spx_plan *plan, void *stream);
 
 /* ---------------------------------------------------------------- batches
- * Many independent products Y_b <- A_b X_b in ONE persistent kernel launch.
- * Each descriptor names one CSR matrix, its right-hand side and its plan
- * options (from an autotuner or spx_plan_default_opts).  csr_batch_create
- * bins every matrix on the device, builds the work-tile list in the caller's
- * workspace and SYNCHRONISES `stream`.  csr_batch_run is a single launch of a
- * counter-reset kernel plus the persistent kernel, capturable into a HIP
- * graph (it uses no memset).  Each matrix's result is bit-identical to
+ * Many independent products Y_b <- A_b X_b in one persistent kernel launch
+ * per lane layout present (the layout follows from each matrix's k: at most
+ * a few launches, whatever the number of matrices).  Each descriptor names
+ * one CSR matrix, its right-hand side and its plan options (from an
+ * autotuner or spx_plan_default_opts).  csr_batch_create bins every matrix on
+ * the device, builds the work-tile list in the caller's workspace and
+ * SYNCHRONISES `stream`.  csr_batch_run launches a queue-reset kernel and
+ * the persistent kernels on `stream`, capturable into a HIP graph (it uses
+ * no memset).  Each matrix's result is bit-identical to
  * csr_spmm (k > 1) or csr_spmv (k = 1) with a plan created from the same
  * options. */
 typedef struct spx_csr_desc {
@@ -220,7 +222,7 @@ spx_status csr_batch_workspace_bytes(int32_t count, const spx_csr_desc *host_des
 spx_status csr_batch_create(int32_t count, const spx_csr_desc *host_descs, void *workspace,
                             size_t ws_bytes, void *stream, spx_batch **out);
 spx_status csr_batch_run(const spx_batch *batch, void *stream);
-/* Tiles, workgroups of the persistent launch, and total split segments. */
+/* Tiles, workgroups of the largest persistent launch, and total split segments. */
 spx_status csr_batch_info(const spx_batch *batch, int64_t *ntiles, int32_t *grid, int64_t *nsegments);
 void csr_batch_destroy(spx_batch *batch);
 
