@@ -359,3 +359,27 @@ def test_memory_probes_run_and_keep_data(spx, torch):
     assert torch.equal(b, torch.ones_like(b))
     with pytest.raises(spx.SpxError):
         spx.probe("gather_rows", a[:8], None, 64)
+
+
+@pytest.mark.parametrize("k", [1, 16])
+def test_nan_inf_stay_in_their_rows(spx, torch, k):
+    """IEEE propagation: a NaN value poisons only its own row; an infinite x
+    entry reaches exactly the rows that reference its column (Inf, or NaN
+    where +Inf and -Inf meet); every other row stays exact.  Checked for each
+    plan variant, including stream bins whose spare slots reload elements."""
+    A = int_valued(matrix("powerlaw", 31), 32)
+    vals = A.values.copy()
+    bad_row = int(np.argmax(np.diff(A.rowptr) == 5))
+    vals[A.rowptr[bad_row] + 2] = np.nan
+    A2 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, vals)
+    X = spgen.small_ints(A.n * k, 33).reshape(A.n, k)
+    hot = int(np.bincount(A.colind, minlength=A.n).argmax())
+    X[hot, :] = np.inf
+    ref = oracle.spmm(A2, X)
+    G = to_gpu(A2)
+    _, plans = plan_variants(spx, A2, k)
+    for name, plan in plans:
+        Xd = dev_vec(torch, X if k > 1 else X[:, 0])
+        Y = spx.spmm(G, Xd, plan=plan) if k > 1 else spx.spmv(G, Xd, plan=plan)
+        Y = Y.cpu().numpy().reshape(A.m, k)
+        assert np.array_equal(Y, ref, equal_nan=True), name
