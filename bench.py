@@ -517,8 +517,8 @@ def bench_c4(ctx):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the products run on one GPU; --gpus {args.gpus} is not supported "
+              "(a row-block sharding over several GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
