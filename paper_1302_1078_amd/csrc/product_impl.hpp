@@ -357,20 +357,26 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
 
 // Stream bin (SpMV only): one workgroup takes kStreamRows consecutive rows of
 // the bin and treats their nonzeros as one flat sequence.  Lanes load that
-// sequence in chunks of kStreamChunk with consecutive lanes on consecutive
-// nonzeros (coalesced, kStreamChunk / 256 independent loads per lane), gather
+// sequence in chunks (stream_chunk) with consecutive lanes on consecutive
+// nonzeros (coalesced, 4 or 8 independent loads per lane), gather
 // x, and park the products in LDS; then every thread sums its own row's
 // products in ascending order.  A chunk costs two dependent global trips for
 // up to 2,048 nonzeros, where a row group pays a trip chain per row.
 constexpr int kStreamRows = 256;
-constexpr int kStreamChunk = 1024;
-constexpr int kStreamPer = kStreamChunk / kWG;
+// Nonzeros per chunk: 8 KB of products in LDS either way (1,024 FP64 or
+// 2,048 FP32 accumulators); measured best for each type.
+template <typename AT>
+constexpr int stream_chunk() {
+  return std::is_same<AT, double>::value ? 1024 : 2048;
+}
 
 template <class C>
 __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, int tile) {
   static_assert(C::KL == 1 && C::VEC == 1, "stream bins serve SpMV only");
   using XT = typename C::XT;
   using AT = typename C::AT;
+  constexpr int kStreamChunk = stream_chunk<AT>();
+  constexpr int kStreamPer = kStreamChunk / kWG;
   __shared__ int32_t s_off[kStreamRows + 1];
   __shared__ int32_t s_p0[kStreamRows];
   __shared__ AT s_prod[kStreamChunk];
