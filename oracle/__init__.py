@@ -286,35 +286,6 @@ def bcsr_bytes(B: BCSR) -> int:
     return 8 * int(B.values.size if B.mask is None else B.values.size) + 4 * nb + 4 * B.browptr.size + extra
 
 
-@dataclass
-class XStage:
-    """Tile-local column lists for staging X in on-chip memory: rows are cut
-    into tiles of `rows` consecutive rows; tile t lists the distinct columns
-    its nonzeros touch, ascending, in ucols[uoff[t]:uoff[t+1]]; lidx[p] is the
-    position of colind[p] in its tile's list."""
-    rows: int
-    uoff: np.ndarray
-    ucols: np.ndarray
-    lidx: np.ndarray
-
-
-def to_xstage(A: CSR, rows: int) -> XStage:
-    """From the definition, one tile at a time."""
-    nt = -(-A.m // rows)
-    uoff = np.zeros(nt + 1, dtype=np.int64)
-    parts = []
-    lidx = np.empty(A.nnz, dtype=np.int64)
-    for t in range(nt):
-        p0, p1 = A.rowptr[t * rows], A.rowptr[min((t + 1) * rows, A.m)]
-        cols = A.colind[p0:p1]
-        u = np.unique(cols)
-        lidx[p0:p1] = np.searchsorted(u, cols)
-        parts.append(u)
-        uoff[t + 1] = uoff[t] + u.size
-    ucols = np.concatenate(parts).astype(np.int32) if parts else np.zeros(0, np.int32)
-    return XStage(rows, uoff.astype(np.int32), ucols, lidx.astype(np.uint16))
-
-
 def max_threads() -> int:
     return int(lib().orc_max_threads())
 

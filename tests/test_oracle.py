@@ -528,27 +528,3 @@ def test_bcsr_bytes_match_the_paper():
         S = oracle.csr_from_coo(8, 8, rr.ravel()[pick], cc.ravel()[pick], np.ones(t))
         blocked = oracle.bcsr_bytes(oracle.to_bcsr(S, 8, 8)) - rowptr_bytes
         assert np.sign(12 * t - blocked) == relation, t
-
-
-# ---------------------------------------------------------------- X staging lists
-
-@pytest.mark.parametrize("rows", [1, 3, 16, 64])
-def test_xstage_lists_rebuild_the_columns(rows):
-    """Each tile's list holds exactly the distinct columns of its rows,
-    ascending, and list[lidx[p]] gives back colind[p] for every nonzero."""
-    rng = np.random.default_rng(70 + rows)
-    for m, n, nnz in [(1, 1, 1), (50, 40, 300), (203, 500, 3000), (10, 10, 0)]:
-        r, c, v = rand_coo(rng, m, n, nnz)
-        A = oracle.csr_from_coo(m, n, r, c, v)
-        S = oracle.to_xstage(A, rows)
-        nt = -(-m // rows)
-        assert S.uoff.size == nt + 1 and S.uoff[-1] == S.ucols.size
-        rebuilt = np.empty(A.nnz, dtype=np.int64)
-        for t in range(nt):
-            u = S.ucols[S.uoff[t]:S.uoff[t + 1]]
-            assert np.all(np.diff(u) > 0)
-            i0, i1 = t * rows, min((t + 1) * rows, m)
-            p0, p1 = A.rowptr[i0], A.rowptr[i1]
-            assert set(u.tolist()) == set(A.colind[p0:p1].tolist())
-            rebuilt[p0:p1] = u[S.lidx[p0:p1].astype(np.int64)]
-        assert np.array_equal(rebuilt, A.colind[:A.nnz])
