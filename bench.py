@@ -498,7 +498,18 @@ def bench_c4(ctx):
         return f
     t_seq32 = float(ctx["timer"].run([seq(mats32, X32, plans32, outs32)], ctx["fsteps"], 3)[:, 0].mean())
     t_seq64 = float(ctx["timer"].run([seq(mats64, X64, plans64, outs64)], ctx["fsteps"], 3)[:, 0].mean())
-    same = all(torch.equal(a, b) for a, b in zip(outs32, B.Ys))
+    # the batch keeps stream bins as stream tiles; single launches of the same
+    # options with that flag must agree bit for bit
+    from paper_1302_1078_amd._lib import PlanOpts, SPX_FLAG_KEEP_STREAM
+    keep = []
+    for o in opts:
+        c = PlanOpts.from_dict(o.to_dict())
+        c.flags |= SPX_FLAG_KEEP_STREAM
+        keep.append(c)
+    outs_chk = [torch.empty_like(Y) for Y in B.Ys]
+    seq(mats32, X32, [spx.Plan.for_matrix(A, o) for A, o in zip(mats32, keep)], outs_chk)()
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(outs_chk, B.Ys))
     info = B.info()
     return {"workload": "256 matrices (64 2D 5-pt, 64 3D 7-pt, 128 Zipf(2.2) mean 8-32), rows "
                         "log-uniform [1e3, 2e5], FP32 values, k in {1, 4, 16}",

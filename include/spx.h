@@ -72,6 +72,9 @@ typedef enum {
 #define SPX_FLAG_SCALAR_X 2u     /* SpMM: one element per lane, no vector loads of X */
 #define SPX_FLAG_NO_XCD_MAP 4u   /* keep hardware workgroup order (no per-XCD contiguous tiles) */
 #define SPX_FLAG_ONE_ROW 8u      /* one row per row group (no multi-row groups for short rows) */
+#define SPX_FLAG_KEEP_STREAM 16u /* SpMV: keep a stream bin as 256-row tiles even when it has fewer
+                                  * than 2 tiles per compute unit (by default such a bin is served
+                                  * by row groups of 8 lanes, which keep more workgroups in flight) */
 typedef struct spx_plan_opts {
   int32_t nbins;
   int32_t upper[SPX_MAX_BINS];
@@ -205,7 +208,8 @@ spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, c
  * the persistent kernels on `stream`, capturable into a HIP graph (it uses
  * no memset).  Each matrix's result is bit-identical to
  * csr_spmm (k > 1) or csr_spmv (k = 1) with a plan created from the same
- * options. */
+ * options plus SPX_FLAG_KEEP_STREAM: the batch fills the device as a whole,
+ * so it keeps every stream bin as 256-row tiles. */
 typedef struct spx_csr_desc {
   int32_t m, n, nnz, k;
   const int32_t *rowptr;

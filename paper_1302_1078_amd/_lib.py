@@ -19,6 +19,7 @@ SPX_FLAG_NO_NT_STORE = 1
 SPX_FLAG_SCALAR_X = 2
 SPX_FLAG_NO_XCD_MAP = 4
 SPX_FLAG_ONE_ROW = 8
+SPX_FLAG_KEEP_STREAM = 16
 
 STATUS_NAMES = {0: "SPX_OK", 1: "SPX_ERR_INVALID", 2: "SPX_ERR_UNSUPPORTED",
                 3: "SPX_ERR_WORKSPACE", 4: "SPX_ERR_HIP"}

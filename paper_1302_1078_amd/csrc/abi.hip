@@ -92,7 +92,7 @@ spx_status product(const char* who, int32_t m, int32_t n, int32_t nnz, const int
   a.k = k;
   int kl, vec;
   layout_for_k(k, xt, X, a.ldx, Y, a.ldy, plan ? plan->opts.flags : 0u, &kl, &vec);
-  if (plan) bins_from_plan(plan, a, kl);
+  if (plan) bins_from_plan(plan, a, kl, true);
   else bins_unbinned(m, nnz, kl, a);
   return launch_product(a, vt, xt, kl, vec, as_stream(stream));
 }

@@ -306,7 +306,7 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
     a.ldx = d.ldx;
     a.ldy = d.ldy;
     a.k = d.k;
-    bins_from_plan(p, a, kl);
+    bins_from_plan(p, a, kl, false);
     for (int j = 0; j < a.nbins; ++j) {
       const BinDesc& bd = a.bins[j];
       if (lid == 0 && bd.rpg > 1) B->multi_row = true;

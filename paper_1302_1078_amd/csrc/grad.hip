@@ -76,10 +76,11 @@ __global__ void k_zero_2d(XT* __restrict__ p, int64_t rows, int32_t k, int64_t l
 
 }  // namespace
 
-// Bin table for the per-nonzero traversals (bins_from_plan with KL = 1).
+// Bin table for the per-nonzero traversals (bins_from_plan with KL = 1; the
+// traversal serves stream bins with 8-lane row groups whatever their size).
 static void grad_bins(const spx_plan* p, int32_t m, int32_t nnz, ProdArgs& a) {
   if (p) {
-    bins_from_plan(p, a, 1);
+    bins_from_plan(p, a, 1, false);
   } else {
     const int32_t k = a.k;
     a.k = 1;

@@ -116,6 +116,7 @@ struct spx_plan {
   int32_t bin_off[SPX_MAX_BINS + 1];  // host copy
   int32_t nsplit;                     // rows in the split bin (0 if none)
   int32_t nseg;                       // total split segments
+  int32_t cus;                        // compute units of the plan's device
   int32_t* row_perm;                  // device, [m]
   int32_t* prange;                    // device, [2 m]: nonzero range of row_perm[i]
   int32_t* seg_row;                   // device, [nseg]
@@ -128,7 +129,10 @@ namespace spx {
 // Launch one fused product over a prepared bin table (product.hip).
 spx_status launch_product(ProdArgs& a, int vt, int xt, int kl, int vec, hipStream_t st);
 // Fill a ProdArgs bin table from a plan, or from the unbinned heuristic.
-void bins_from_plan(const spx_plan* plan, ProdArgs& a, int kl);
+// `own_launch`: the table drives a launch of its own (not a tile list shared
+// with other matrices), so a stream bin too small to fill the device is
+// served by row groups instead (unless SPX_FLAG_KEEP_STREAM).
+void bins_from_plan(const spx_plan* plan, ProdArgs& a, int kl, bool own_launch);
 void bins_unbinned(int32_t m, int32_t nnz, int kl, ProdArgs& a);
 int lanes_valid(int lanes);
 // Lanes per X row (KL) and elements per lane (VEC) for k right-hand sides.

@@ -308,6 +308,13 @@ extern "C" spx_status csr_plan_create(int32_t m, int32_t n, int32_t nnz, const i
   }
   p->nsplit = 0;
   p->nseg = 0;
+  p->cus = 0;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      p->cus = cus;
+  }
   if (has_split(*opts)) {
     const int nb = opts->nbins;
     const int32_t nsplit = p->bin_off[nb] - p->bin_off[nb - 1];
@@ -368,7 +375,13 @@ extern "C" void csr_plan_destroy(spx_plan* p) { delete p; }
 
 namespace spx {
 
-void bins_from_plan(const spx_plan* p, ProdArgs& a, int kl) {
+// A stream bin with fewer tiles than this many per compute unit leaves most
+// of the device idle (one 256-row workgroup per CU cannot hide the gather
+// latency); row groups of kSmallStreamLanes lanes give 8x the workgroups.
+constexpr int kStreamTilesPerCU = 2;
+constexpr int kSmallStreamLanes = 8;
+
+void bins_from_plan(const spx_plan* p, ProdArgs& a, int kl, bool own_launch) {
   const spx_plan_opts& o = p->opts;
   int32_t blk = 0;
   int out = 0;
@@ -378,6 +391,9 @@ void bins_from_plan(const spx_plan* p, ProdArgs& a, int kl) {
     int32_t lanes = o.lanes[b];
     const bool stream = (lanes == SPX_LANES_STREAM);
     if (stream && !(kl == 1 && a.k == 1)) lanes = 1;  // SpMM: row groups of KL lanes
+    if (stream && lanes == SPX_LANES_STREAM && own_launch && !(o.flags & SPX_FLAG_KEEP_STREAM) &&
+        (static_cast<int64_t>(rows) + kWG - 1) / kWG < static_cast<int64_t>(kStreamTilesPerCU) * p->cus)
+      lanes = kSmallStreamLanes;
     const int32_t units = (lanes == 0) ? p->nseg : rows;
     if (units == 0) continue;
     // short-row bins (every row fits one nonzero per slot) serve 4 rows per

@@ -71,6 +71,14 @@ def single_bin_opts(lanes: int, k: int = 1, chunk: int = 512, kahan: int = 256):
     return o
 
 
+def keep_stream(o):
+    """Serve stream bins as 256-row tiles even on matrices too small to fill
+    the device (test matrices are)."""
+    from paper_1302_1078_amd._lib import SPX_FLAG_KEEP_STREAM
+    o.flags |= SPX_FLAG_KEEP_STREAM
+    return o
+
+
 def two_bin_opts(split_above: int, lanes: int, k: int = 1, chunk: int = 512, kahan: int = 256):
     import paper_1302_1078_amd as spx
     o = spx.PlanOpts()

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import spgen
-from _cases import gamma, single_bin_opts, two_bin_opts
+from _cases import gamma, keep_stream, single_bin_opts, two_bin_opts
 
 pytestmark = pytest.mark.gpu
 
@@ -72,7 +72,8 @@ def test_batch_bit_identical_to_single(spx, torch, dtype_name):
     info = B.info()
     assert info["tiles"] > 0 and info["grid"] > 0
     for i, (A, X) in enumerate(zip(mats, Xs)):
-        want = single(spx, A, X, opts[i]).cpu().numpy()
+        # the batch keeps stream bins as stream tiles whatever the matrix size
+        want = single(spx, A, X, keep_stream(spx.PlanOpts.from_dict(opts[i].to_dict()))).cpu().numpy()
         got = Ys[i].cpu().numpy()
         u = np.uint32 if dtype == torch.float32 else np.uint64
         assert np.array_equal(got.view(u), want.view(u)), (i, specs[i])

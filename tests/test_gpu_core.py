@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import spgen
-from _cases import KINDS, int_valued, matrix, single_bin_opts, stream_mm_opts, to_gpu, two_bin_opts
+from _cases import KINDS, int_valued, keep_stream, matrix, single_bin_opts, stream_mm_opts, to_gpu, two_bin_opts
 
 pytestmark = pytest.mark.gpu
 
@@ -34,16 +34,19 @@ def dev_vec(torch, a, dtype=None):
 
 
 def plan_variants(spx, A, k=1):
-    """(name, plan) pairs: none, default, and one plan per lane width."""
+    """(name, plan) pairs: none, default (its stream bin served by row groups,
+    as on any matrix this small, and kept as stream tiles), and one plan per
+    lane width."""
     G = to_gpu(A)
-    out = [("none", None), ("default", spx.Plan.for_matrix(G, spx.default_opts(k)))]
+    out = [("none", None), ("default", spx.Plan.for_matrix(G, spx.default_opts(k))),
+           ("default-stream", spx.Plan.for_matrix(G, keep_stream(spx.default_opts(k))))]
     for lanes in (1, 2, 4, 8, 16, 32, 64, 256, 512):
-        out.append((f"lanes{lanes}", spx.Plan.for_matrix(G, single_bin_opts(lanes, k))))
+        out.append((f"lanes{lanes}", spx.Plan.for_matrix(G, keep_stream(single_bin_opts(lanes, k)))))
     out.append(("sub-bins", spx.Plan.for_matrix(G, spx.PlanOpts.from_dict(
         {"nbins": 7, "upper": [1, 2, 4, 8, 16, 32], "lanes": [1, 2, 4, 8, 16, 32, 256],
          "max_k": k}))))
-    out.append(("stream+split", spx.Plan.for_matrix(G, spx.PlanOpts.from_dict(
-        {"nbins": 2, "upper": [40], "lanes": [512, 0], "split_chunk": 256, "max_k": k}))))
+    out.append(("stream+split", spx.Plan.for_matrix(G, keep_stream(spx.PlanOpts.from_dict(
+        {"nbins": 2, "upper": [40], "lanes": [512, 0], "split_chunk": 256, "max_k": k})))))
     out.append(("split", spx.Plan.for_matrix(G, single_bin_opts(0, k, chunk=256))))
     out.append(("lanes8+split", spx.Plan.for_matrix(G, two_bin_opts(300, 8, k, chunk=256))))
     return G, out
@@ -178,7 +181,7 @@ def test_spmv_deterministic(spx, torch):
     A = matrix("powerlaw_sq", seed=9)
     G = to_gpu(A)
     xd = dev_vec(torch, spgen.uniform(A.n, 2))
-    for o in (spx.default_opts(1), single_bin_opts(0, chunk=256)):
+    for o in (spx.default_opts(1), keep_stream(spx.default_opts(1)), single_bin_opts(0, chunk=256)):
         plan = spx.Plan.for_matrix(G, o)
         ys = [spx.spmv(G, xd, plan=plan).cpu().numpy().view(np.uint64) for _ in range(4)]
         assert all(np.array_equal(ys[0], y) for y in ys[1:])

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import spgen
-from _cases import gamma, int_valued, matrix, single_bin_opts, stream_mm_opts, to_gpu, two_bin_opts
+from _cases import gamma, int_valued, keep_stream, matrix, single_bin_opts, stream_mm_opts, to_gpu, two_bin_opts
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +76,7 @@ def test_precision_spmv_bounds(spx, torch, kind, vdtype):
     y3 = oracle.spmv(A, x)
     L = A.row_lengths()
     for name, opts in [("default", spx.default_opts(1, torch.float32)),
+                       ("default-stream", keep_stream(spx.default_opts(1, torch.float32))),
                        ("block", single_bin_opts(256)), ("split", single_bin_opts(0, chunk=256)),
                        ("wave+split", two_bin_opts(300, 64, chunk=512))]:
         plan = spx.Plan.for_matrix(G, opts)
