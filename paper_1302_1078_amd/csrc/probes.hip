@@ -64,11 +64,17 @@ __device__ __forceinline__ uint32_t scramble(uint32_t v) {  // an integer hash (
   return v;
 }
 
+// A hash mapped onto [0, n) by its high product word (multiply-shift range
+// reduction): one instruction, so the probe's own arithmetic stays far below
+// its memory time (a 64-bit remainder here cost about 90 instructions per
+// element).
+__device__ __forceinline__ uint32_t below(uint32_t h, uint32_t n) { return __umulhi(h, n); }
+
 template <bool ROWS>
-__global__ __launch_bounds__(kWG) void k_probe_gather(const double* __restrict__ p, int64_t n, double* out) {
+__global__ __launch_bounds__(kWG) void k_probe_gather(const double* __restrict__ p, uint32_t n, double* out) {
   const int lane = threadIdx.x % kWave;
   const uint32_t wave = blockIdx.x * (kWG / kWave) + threadIdx.x / kWave;
-  const int64_t rows = n / 16;  // 128-byte rows
+  const uint32_t rows = n / 16;  // 128-byte rows
   double acc = 0.0;
   for (int it = 0; it < kGatherIters; it += 4) {
     d2 v[4];
@@ -76,10 +82,10 @@ __global__ __launch_bounds__(kWG) void k_probe_gather(const double* __restrict__
     for (int u = 0; u < 4; ++u) {
       const uint32_t h = scramble(wave * 977u + static_cast<uint32_t>(it + u) * 131u);
       if (ROWS) {
-        const int64_t r = scramble(h + lane / 8) % rows;
-        v[u] = *reinterpret_cast<const d2*>(p + r * 16 + (lane % 8) * 2);
+        const uint32_t r = below(scramble(h + lane / 8), rows);
+        v[u] = *reinterpret_cast<const d2*>(p + static_cast<size_t>(r) * 16 + (lane % 8) * 2);
       } else {
-        v[u] = d2{p[scramble(h + lane) % n], 0.0};
+        v[u] = d2{p[below(scramble(h + lane), n)], 0.0};
       }
     }
 #pragma unroll
@@ -116,8 +122,10 @@ extern "C" spx_status spx_probe(int32_t kind, void* buf, void* buf2, size_t byte
     case 6: {
       const int64_t elems = static_cast<int64_t>(bytes / 8);
       if ((kind == 5 && elems < 16) || elems < 1) return fail(SPX_ERR_INVALID, "spx_probe: gather buffer too small");
-      if (kind == 5) k_probe_gather<true><<<g, kWG, 0, st>>>(static_cast<const double*>(buf), elems, static_cast<double*>(buf2));
-      else k_probe_gather<false><<<g, kWG, 0, st>>>(static_cast<const double*>(buf), elems, static_cast<double*>(buf2));
+      if (elems > 0xffffffffLL) return fail(SPX_ERR_INVALID, "spx_probe: gather buffer above 2^32 elements");
+      const uint32_t ne = static_cast<uint32_t>(elems);
+      if (kind == 5) k_probe_gather<true><<<g, kWG, 0, st>>>(static_cast<const double*>(buf), ne, static_cast<double*>(buf2));
+      else k_probe_gather<false><<<g, kWG, 0, st>>>(static_cast<const double*>(buf), ne, static_cast<double*>(buf2));
       break;
     }
     default: return fail(SPX_ERR_INVALID, "spx_probe: kind=%d", kind);
