@@ -110,6 +110,35 @@ class Timer:
         return np.array([[e[i].elapsed_time(e[i + 1]) * 1e-3 for i in range(len(fns))] for e in evs])
 
 
+def chase_latency(torch, spx, dev):
+    """ns per dependent load, from pointer chases over a random cycle of
+    128-byte lines in a 1 GiB buffer.  A chase of H hops touches H lines; run
+    warm (the same path just walked), 2 MB of lines stay in L2 and 16 MB miss
+    the 4 MB L2 but stay in the Infinity Cache; run after a 1 GiB flush, every
+    line comes from HBM.  "one address": all lanes on one chain; "64 chains":
+    one gather of 64 lines per hop (the SpMV x access)."""
+    import numpy as np
+    from paper_1302_1078_amd.ops import chase_cycle, probe_chase
+    n = 1 << 28
+    nxt = chase_cycle(n, dev, seed=1)
+    one = torch.zeros(64, dtype=torch.int32, device=dev)
+    # 64 starts spread along the cycle (each walked from its own slot)
+    many = torch.empty(64, dtype=torch.int32, device=dev)
+    i = torch.zeros(1, dtype=torch.int32, device=dev)
+    for lane in range(64):
+        many[lane] = i[0]
+        i = probe_chase(nxt, i.repeat(64), 1 << 12)[:1]
+    cases = (("L2", one, 16384, False), ("infinity_cache", one, 131072, False), ("HBM", one, 16384, True),
+             ("L2_gather64", many, 256, False), ("HBM_gather64", many, 1024, True))
+    out = {}
+    for label, start, hops, cold in cases:
+        fn = lambda start=start, hops=hops: probe_chase(nxt, start, hops)  # noqa: E731
+        t = float(np.median(Timer(torch, dev, cold).run([fn], 3, 1)[:, 0]))
+        out[label + "_ns"] = t / hops * 1e9
+    del nxt
+    return out
+
+
 def app_bytes(m, n, nnz, k=1, sv=8, sx=8):
     return (sv + 4) * nnz + sx * k * n + sx * k * m + 4 * (m + 1)
 
@@ -596,6 +625,7 @@ def main():
     gather["spmm_x_rows_g_per_s"] = nnz / float(tm.mean()) / 1e9
     gather["spmv_x_elems_g_per_s"] = nnz / float(tv.mean()) / 1e9
     detail["gather_ceiling"] = gather
+    detail["latency"] = chase_latency(torch, spx, dev)
 
     cpu = None
     if not args.no_cpu:

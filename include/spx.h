@@ -320,6 +320,28 @@ spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int32_t bitmap,
  * workgroups of 256 threads. */
 spx_status spx_probe(int32_t kind, void *buf, void *buf2, size_t bytes, int32_t blocks, void *stream);
 
+/* The x access of an SpMV in isolation (Sec. 4.2 attributes SpMV time to the
+ * x gather): idx int32[nidx] is streamed (non-temporal loads, as the products
+ * stream colind) and, with gather != 0, x[idx[p]] is read through L2 for every
+ * p; with gather == 0 only the index stream is read.  blocks workgroups (a
+ * positive multiple of 8) each take one contiguous range of idx, XCD-
+ * contiguous like the product tiles, and write the sum of what they read to
+ * sink[tile] (f64[blocks]; per-workgroup sums in a fixed order).  With
+ * gather != 0, entries outside [0, n) are skipped (not read).  Counter runs of the two modes
+ * separate the gather's L2 hits and misses from the index stream's. */
+spx_status spx_probe_index_gather(const int32_t *idx, int64_t nidx, const double *x, int32_t n,
+                                  int32_t gather, double *sink, int32_t blocks, void *stream);
+
+/* Load-to-use latency (the paper's latency argument, Sec. 4.2): one wavefront
+ * whose lane l follows i <- next[i] & (n - 1) from start[l] for `hops`
+ * dependent loads and writes its final index to out[l] (int32[64]).  next is
+ * int32[n] with n a power of two (a single random cycle gives one new line
+ * per hop); start int32[64] (equal entries: one address per load; distinct
+ * entries: 64 independent chains, one gather per hop).  Time / hops is the
+ * latency per dependent load of a working set of 4n bytes. */
+spx_status spx_probe_chase(const int32_t *next, int64_t n, const int32_t *start, int64_t hops, int32_t *out,
+                           void *stream);
+
 #ifdef __cplusplus
 }
 #endif

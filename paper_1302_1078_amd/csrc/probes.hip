@@ -94,10 +94,87 @@ __global__ __launch_bounds__(kWG) void k_probe_gather(const double* __restrict__
   if (out && acc == 12345.678) out[0] = acc;
 }
 
+// Index-driven gather: the x access of an SpMV without its values.  Workgroup
+// b serves one contiguous range of idx (XCD-contiguous like the product
+// tiles); its lanes stream idx with non-temporal loads, 4 per lane in flight,
+// and add x[idx[p]] (GATHER) or idx[p] itself (the index stream alone).  Each
+// workgroup writes its partial sum to sink[tile], so the result is
+// deterministic and every load stays live.
+template <bool GATHER>
+__global__ __launch_bounds__(kWG) void k_probe_idx(const int32_t* __restrict__ idx, int64_t nidx,
+                                                   const double* __restrict__ x, int32_t n, int64_t per,
+                                                   double* __restrict__ sink) {
+  __shared__ double part[kWG / kWave];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t b = static_cast<int64_t>(tile) * per;
+  const int64_t e = (b + per < nidx) ? b + per : nidx;
+  double acc = 0.0;
+  for (int64_t p = b + threadIdx.x; p < e; p += 4 * kWG) {
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = (p + u * kWG < e) ? ld_stream(idx + p + u * kWG) : -1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (c[u] < 0) continue;  // past the range
+      if (GATHER) {
+        if (c[u] < n) acc += x[c[u]];  // an index outside x is skipped, never read
+      } else {
+        acc += static_cast<double>(c[u]);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kWG / kWave; ++w) s += part[w];
+    sink[tile] = s;
+  }
+}
+
+// Pointer chase: one wavefront; lane l starts at start[l] and follows
+// i <- next[i] & mask for `hops` dependent loads, then writes its final index
+// to out[l].  The mask keeps every load inside the buffer whatever it holds.
+__global__ __launch_bounds__(kWave) void k_probe_chase(const int32_t* __restrict__ next, uint32_t mask,
+                                                       const int32_t* __restrict__ start, int64_t hops,
+                                                       int32_t* __restrict__ out) {
+  uint32_t i = static_cast<uint32_t>(start[threadIdx.x]) & mask;
+  for (int64_t h = 0; h < hops; ++h) i = static_cast<uint32_t>(next[i]) & mask;
+  out[threadIdx.x] = static_cast<int32_t>(i);
+}
+
 }  // namespace
 }  // namespace spx
 
 using namespace spx;
+
+extern "C" spx_status spx_probe_index_gather(const int32_t* idx, int64_t nidx, const double* x, int32_t n,
+                                             int32_t gather, double* sink, int32_t blocks, void* stream) {
+  if (nidx < 0 || n < 0) return fail(SPX_ERR_INVALID, "spx_probe_index_gather: negative size");
+  if (blocks <= 0 || (blocks & 7)) return fail(SPX_ERR_INVALID, "spx_probe_index_gather: blocks=%d (a positive multiple of 8)", blocks);
+  if (!sink) return fail(SPX_ERR_INVALID, "spx_probe_index_gather: sink is null");
+  if (nidx > 0 && (!idx || (gather && !x))) return fail(SPX_ERR_INVALID, "spx_probe_index_gather: null input");
+  if (gather && nidx > 0 && n == 0) return fail(SPX_ERR_INVALID, "spx_probe_index_gather: gather from an empty x");
+  const int64_t per = (nidx + blocks - 1) / blocks;
+  hipStream_t st = as_stream(stream);
+  if (gather) k_probe_idx<true><<<static_cast<unsigned>(blocks), kWG, 0, st>>>(idx, nidx, x, n, per, sink);
+  else k_probe_idx<false><<<static_cast<unsigned>(blocks), kWG, 0, st>>>(idx, nidx, x, n, per, sink);
+  SPX_LAUNCHED("spx_probe_index_gather");
+  return SPX_OK;
+}
+
+extern "C" spx_status spx_probe_chase(const int32_t* next, int64_t n, const int32_t* start, int64_t hops,
+                                      int32_t* out, void* stream) {
+  if (n < 1 || n > (int64_t(1) << 31) || (n & (n - 1)))
+    return fail(SPX_ERR_INVALID, "spx_probe_chase: n=%lld is not a power of two in [1, 2^31]", (long long)n);
+  if (hops < 0) return fail(SPX_ERR_INVALID, "spx_probe_chase: hops < 0");
+  if (!next || !start || !out) return fail(SPX_ERR_INVALID, "spx_probe_chase: null pointer");
+  k_probe_chase<<<1, kWave, 0, as_stream(stream)>>>(next, static_cast<uint32_t>(n - 1), start, hops, out);
+  SPX_LAUNCHED("spx_probe_chase");
+  return SPX_OK;
+}
 
 // kind: 0 read, 1 write, 2 write non-temporal, 3 copy (src = buf, dst = buf2),
 // 4 flush (read-modify-write), 5 random 128-byte row gather, 6 random 8-byte

@@ -428,3 +428,49 @@ def probe(kind: str, buf: torch.Tensor, buf2: torch.Tensor | None = None, blocks
     _dev(buf, buf2)
     check(_lib.load().spx_probe(PROBE_KINDS[kind], _ptr(buf), _ptr(buf2), buf.numel() * buf.element_size(),
                                 blocks, _stream()), "spx_probe")
+
+
+def probe_index_gather(idx: torch.Tensor, x: torch.Tensor | None, gather: bool = True,
+                       blocks: int = 4096, sink: torch.Tensor | None = None) -> torch.Tensor:
+    """Stream idx and (gather=True) read x[idx[p]] (spx_probe_index_gather);
+    returns the per-workgroup sums, f64[blocks]."""
+    _dev(idx, x)
+    if idx.dtype != torch.int32 or (x is not None and x.dtype != torch.float64):
+        raise TypeError("probe_index_gather: idx int32, x float64")
+    _contig(idx)
+    if sink is None:
+        sink = torch.zeros(blocks, dtype=torch.float64, device=idx.device)
+    n = x.numel() if x is not None else 0
+    check(_lib.load().spx_probe_index_gather(_ptr(idx), idx.numel(), _ptr(x), n, int(gather), _ptr(sink),
+                                             blocks, _stream()), "spx_probe_index_gather")
+    return sink
+
+
+def chase_cycle(n: int, device, seed: int = 0, stride: int = 32) -> torch.Tensor:
+    """next int32[n]: one random cycle through the n / stride slots that are
+    multiples of `stride` (one per 128-byte line at the default), built on
+    the device; the other slots hold 0 and are never visited from a slot of
+    the cycle."""
+    if n % stride:
+        raise ValueError("chase_cycle: n must be a multiple of stride")
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    perm = torch.randperm(n // stride, generator=g, device=device, dtype=torch.int64) * stride
+    nxt = torch.zeros(n, dtype=torch.int32, device=device)
+    nxt[perm] = torch.roll(perm, -1).to(torch.int32)
+    return nxt
+
+
+def probe_chase(nxt: torch.Tensor, start: torch.Tensor, hops: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Follow nxt from start[l] for `hops` dependent loads per lane
+    (spx_probe_chase); returns the 64 final indices."""
+    _dev(nxt, start)
+    if nxt.dtype != torch.int32 or start.dtype != torch.int32 or start.numel() < 64:
+        raise TypeError("probe_chase: nxt int32[n], start int32[64]")
+    _contig(nxt)
+    _contig(start)
+    if out is None:
+        out = torch.empty(64, dtype=torch.int32, device=nxt.device)
+    check(_lib.load().spx_probe_chase(_ptr(nxt), nxt.numel(), _ptr(start), hops, _ptr(out), _stream()),
+          "spx_probe_chase")
+    return out

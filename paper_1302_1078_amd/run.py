@@ -19,7 +19,9 @@ import sys
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c3", "stencil27"])
-    ap.add_argument("--op", default="spmv", choices=["spmv", "spmm"])
+    ap.add_argument("--op", default="spmv", choices=["spmv", "spmm", "xgather", "colstream"],
+                    help="xgather / colstream: the index-gather probe over the matrix's colind "
+                         "(with / without the x reads)")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--reps", type=int, default=5)
@@ -56,12 +58,21 @@ def main(argv=None):
     vt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[args.dtype]
     xt = torch.float64 if args.dtype == "f64" else torch.float32
     A = A.with_values(A.values.to(vt))
-    k = 1 if args.op == "spmv" else args.k
+    k = args.k if args.op == "spmm" else 1
     X = torch.from_numpy(spgen.uniform(A.n * k, 0)).to(dev).to(xt)
     X = X if k > 1 else X.reshape(-1)
     X = X.reshape(A.n, k) if k > 1 else X
     Y = torch.empty((A.m, k) if k > 1 else (A.m,), dtype=xt, device=dev)
     flush = None if args.no_flush else torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+    if args.op in ("xgather", "colstream"):
+        x = torch.from_numpy(spgen.uniform(A.n, 0)).to(dev)
+        for _ in range(args.reps):
+            if flush is not None:
+                ops.probe("flush", flush)
+            ops.probe_index_gather(A.colind, x, gather=args.op == "xgather", blocks=4096)
+        torch.cuda.synchronize()
+        print(f"ran {args.op} on {args.workload} ({A.nnz} indices) x{args.reps}", flush=True)
+        return
     plans = [ops.Plan.for_matrix(A, ops.default_opts(k, vt))]
     for l in [int(s) for s in args.lanes.split(",") if s.strip()]:
         plans.append(ops.Plan.for_matrix(A, PlanOpts.from_dict({"nbins": 1, "upper": [], "lanes": [l],

@@ -364,6 +364,51 @@ def test_memory_probes_run_and_keep_data(spx, torch):
         spx.probe("gather_rows", a[:8], None, 64)
 
 
+@pytest.mark.parametrize("nidx", [0, 1, 999, 70_001])
+def test_index_gather_probe_sums(spx, torch, nidx):
+    """The index-gather probe reads exactly idx (and x[idx]) once each: the
+    per-workgroup sums match the host's over the same contiguous ranges
+    (exact for the index stream; FP64 rounding for the gather)."""
+    from paper_1302_1078_amd.ops import probe_index_gather
+    n = 5_000
+    rng = np.random.default_rng(nidx)
+    idx = rng.integers(0, n, nidx).astype(np.int32)
+    x = spgen.uniform(n, 3)
+    blocks = 64
+    per = -(-nidx // blocks) if nidx else 0
+    want_i = np.array([idx[t * per:(t + 1) * per].astype(np.float64).sum() for t in range(blocks)])
+    want_x = np.array([x[idx[t * per:(t + 1) * per]].sum() for t in range(blocks)])
+    idx_d, x_d = dev_vec(torch, idx), dev_vec(torch, x)
+    got_i = probe_index_gather(idx_d, x_d, gather=False, blocks=blocks).cpu().numpy()
+    got_x = probe_index_gather(idx_d, x_d, gather=True, blocks=blocks).cpu().numpy()
+    assert np.array_equal(got_i, want_i)
+    assert np.allclose(got_x, want_x, rtol=1e-12, atol=1e-12)
+    with pytest.raises(spx.SpxError):
+        probe_index_gather(idx_d, x_d, blocks=12)  # not a multiple of 8
+
+
+def test_chase_probe_follows_the_cycle(spx, torch):
+    """The chase probe's 64 lanes end where the host walk of the same cycle
+    ends, from one shared start and from 64 distinct starts."""
+    from paper_1302_1078_amd.ops import chase_cycle, probe_chase
+    n, hops = 1 << 12, 1_000
+    nxt = chase_cycle(n, "cuda:0", seed=5, stride=4)
+    h = nxt.cpu().numpy()
+    seen, i = 1, int(h[0])
+    while i != 0:  # one cycle through every 4th slot
+        assert i % 4 == 0
+        i, seen = int(h[i]), seen + 1
+    assert seen == n // 4
+    for starts in (np.zeros(64, np.int32), (np.arange(64) * 61).astype(np.int32)):
+        want = starts.copy()
+        for _ in range(hops):
+            want = h[want]
+        out = probe_chase(nxt, dev_vec(torch, starts), hops).cpu().numpy()
+        assert np.array_equal(out, want)
+    with pytest.raises(spx.SpxError):
+        probe_chase(nxt[:1000], dev_vec(torch, np.zeros(64, np.int32)), 10)  # n not a power of two
+
+
 @pytest.mark.parametrize("k", [1, 16])
 def test_nan_inf_stay_in_their_rows(spx, torch, k):
     """IEEE propagation: a NaN value poisons only its own row; an infinite x
