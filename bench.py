@@ -352,9 +352,10 @@ def bench_occupancy(ctx, A1=None):
 # ---------------------------------------------------------------- RCM ordering (Sec. 4.4)
 
 def bench_rcm(ctx, A1=None):
-    """Products before and after reverse Cuthill-McKee ordering (Sec. 4.4):
-    the 27-point stencil in its natural order, randomly relabeled, and the
-    relabeled matrix reordered by RCM; the power-law matrix as generated and
+    """Products before and after reverse Cuthill-McKee ordering (Sec. 4.4)
+    and degree ordering (columns, and rows with them, by descending column
+    count): the 27-point stencil in its natural order, randomly relabeled,
+    and the relabeled matrix reordered; the power-law matrix as generated and
     reordered.  Reports time, UCLD and vector access (x lines of 128 B, rows
     dealt to 8 XCD caches in contiguous eighths, the tile map's layout)."""
     torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
@@ -375,8 +376,12 @@ def bench_rcm(ctx, A1=None):
         R = spx.permute(src, perm)
         torch.cuda.synchronize()
         permute_s = time.time() - t0
+        t0 = time.time()
+        Dg = spx.permute(src, spx.degree_order(src))
+        torch.cuda.synchronize()
+        degree_s = time.time() - t0
         rows = {}
-        for oname, A in orders + [(f"rcm_of_{src_name}", R)]:
+        for oname, A in orders + [(f"rcm_of_{src_name}", R), (f"degree_of_{src_name}", Dg)]:
             m, n, nnz = A.m, A.n, A.nnz
             r = {"ucld_line16": spx.ucld(A, 16),
                  "vector_access_8xcd": spx.vector_access(A, 16, 8, -(-m // 8)),
@@ -396,8 +401,9 @@ def bench_rcm(ctx, A1=None):
                 r[f"k{k}_us"] = t * 1e6
                 r[f"k{k}_gflops"] = 2 * nnz * k / t / 1e9
             rows[oname] = r
-        out[name] = {"orders": rows, "rcm_host_s": round(rcm_s, 2), "permute_device_s": round(permute_s, 3)}
-        del R, perm
+        out[name] = {"orders": rows, "rcm_host_s": round(rcm_s, 2), "permute_device_s": round(permute_s, 3),
+                     "degree_order_and_permute_device_s": round(degree_s, 3)}
+        del R, perm, Dg
         torch.cuda.empty_cache()
     return out
 

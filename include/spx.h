@@ -257,6 +257,18 @@ spx_status csr_permute(int32_t m, int32_t nnz, const int32_t *rowptr, const int3
                        int32_t *colind_out, double *values_out, int32_t *nnz_out, void *workspace,
                        size_t ws_bytes, void *stream);
 
+/* Degree ordering: columns by descending number of nonzeros, ties in
+ * ascending index; perm int32[n] receives perm[new] = old.  For a square
+ * matrix, csr_permute with this perm relabels rows and columns together, so
+ * the most-referenced x entries share cache lines (an alternative to the
+ * paper's RCM step, Sec. 4.4, for matrices whose column use is skewed rather
+ * than banded).  colind int32[nnz] on the device; entries outside [0, n) are
+ * not counted.  Workspace: csr_degree_order_workspace_bytes.  Asynchronous
+ * on `stream`. */
+spx_status csr_degree_order_workspace_bytes(int32_t n, int32_t nnz, size_t *bytes);
+spx_status csr_degree_order(int32_t n, int32_t nnz, const int32_t *colind, int32_t *perm, void *workspace,
+                            size_t ws_bytes, void *stream);
+
 /* Vector access (Sec. 4.2, Sec. 4.4): the expected number of times x is moved
  * from memory when rows are dealt round-robin, in chunks of `chunk`
  * consecutive rows, to `parts` caches that never evict: distinct (part,

@@ -18,6 +18,8 @@ Functions and the passages they follow:
   byte count (Sec. 4.2 for SpMV, Sec. 5 for SpMM), generalised to element
   sizes and non-square shapes.
 * ``ucld``           -- useful cacheline density (Sec. 4.1).
+* ``degree_order``   -- columns by descending nonzero count, ties ascending
+  (a locality ordering set beside the paper's RCM step, Sec. 4.4).
 
 Parity: each function is pinned in ``tests/test_oracle.py`` against brute
 force, invariants or closed forms; none is "parity unpinned".
@@ -198,6 +200,15 @@ def rcm(A: CSR) -> np.ndarray:
     if lib().orc_rcm(A.m, A.n, _p(A.rowptr), _p(_i32(A.colind)), _p(perm)) != 0:
         raise ValueError("rcm needs a square matrix")
     return perm
+
+
+def degree_order(A: CSR) -> np.ndarray:
+    """Columns listed by descending number of nonzeros, equal counts in
+    ascending column index; perm[new] = old (n entries)."""
+    count = [0] * A.n
+    for c in np.asarray(A.colind).tolist():
+        count[c] += 1
+    return np.array(sorted(range(A.n), key=lambda j: (-count[j], j)), dtype=np.int32)
 
 
 def permute(A: CSR, perm) -> CSR:

@@ -104,6 +104,8 @@ SIGNATURES = {
     "csr_batch_info": (ctypes.c_int, [P, P, P, P]),
     "csr_batch_destroy": (None, [P]),
     "csr_rcm": (ctypes.c_int, [i32, i32, i32, P, P, P]),
+    "csr_degree_order_workspace_bytes": (ctypes.c_int, [i32, i32, SZ]),
+    "csr_degree_order": (ctypes.c_int, [i32, i32, P, P, P, ctypes.c_size_t, P]),
     "csr_permute_workspace_bytes": (ctypes.c_int, [i32, i32, SZ]),
     "csr_permute": (ctypes.c_int, [i32, i32, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]),
     "csr_vector_access": (ctypes.c_int, [i32, i32, i32, P, P, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]),

@@ -251,8 +251,60 @@ __global__ void k_relabel(const int32_t* __restrict__ rowptr, const int32_t* __r
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Nonzeros per column (entries outside [0, n) are not counted).
+__global__ void k_col_count(const int32_t* __restrict__ colind, int64_t nnz, int32_t n,
+                            int32_t* __restrict__ cnt) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t c = colind[p];
+  if (c >= 0 && c < n) atomicAdd(cnt + c, 1);
+}
+
+// Sort keys: the complemented count, so an ascending stable sort lists
+// columns by descending count with ties in ascending index; values = index.
+__global__ void k_degree_keys(const int32_t* __restrict__ cnt, int32_t n, uint32_t* __restrict__ keys,
+                              int32_t* __restrict__ idx) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  keys[j] = ~static_cast<uint32_t>(cnt[j]);
+  idx[j] = static_cast<int32_t>(j);
+}
+
 }  // namespace
 }  // namespace spx
+
+extern "C" spx_status csr_degree_order_workspace_bytes(int32_t n, int32_t nnz, size_t* bytes) {
+  if (!bytes || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_degree_order_workspace_bytes: bad argument");
+  *bytes = 2 * align256(sizeof(int32_t) * static_cast<size_t>(n > 0 ? n : 1)) + radix_workspace_bytes(n, 4);
+  return SPX_OK;
+}
+
+extern "C" spx_status csr_degree_order(int32_t n, int32_t nnz, const int32_t* colind, int32_t* perm,
+                                       void* workspace, size_t ws_bytes, void* stream) {
+  if (n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_degree_order: negative size");
+  if ((n > 0 && !perm) || (nnz > 0 && !colind)) return fail(SPX_ERR_INVALID, "csr_degree_order: null pointer");
+  size_t need = 0;
+  spx_status s = csr_degree_order_workspace_bytes(n, nnz, &need);
+  if (s != SPX_OK) return s;
+  if (!workspace || ws_bytes < need)
+    return fail(SPX_ERR_WORKSPACE, "csr_degree_order: workspace %zu < %zu bytes", ws_bytes, need);
+  if (n == 0) return SPX_OK;
+  hipStream_t st = as_stream(stream);
+  char* w = static_cast<char*>(workspace);
+  int32_t* cnt = reinterpret_cast<int32_t*>(w);
+  w += align256(sizeof(int32_t) * static_cast<size_t>(n));
+  uint32_t* keys = reinterpret_cast<uint32_t*>(w);
+  w += align256(sizeof(int32_t) * static_cast<size_t>(n));
+  k_set_i32<<<blocks_for(n), 256, 0, st>>>(cnt, n, 0);
+  SPX_LAUNCHED("k_set_i32");
+  if (nnz > 0) {
+    k_col_count<<<blocks_for(nnz), 256, 0, st>>>(colind, nnz, n, cnt);
+    SPX_LAUNCHED("k_col_count");
+  }
+  k_degree_keys<<<blocks_for(n), 256, 0, st>>>(cnt, n, keys, perm);
+  SPX_LAUNCHED("k_degree_keys");
+  return radix_sort_u32(keys, perm, n, 32, w, st);
+}
 
 extern "C" spx_status csr_permute_workspace_bytes(int32_t m, int32_t nnz, size_t* bytes) {
   if (!bytes || m < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_permute_workspace_bytes: bad argument");

@@ -303,6 +303,20 @@ def rcm(A: CSR) -> torch.Tensor:
     return perm.to(A.device)
 
 
+def degree_order(A: CSR) -> torch.Tensor:
+    """Columns by descending nonzero count, ties ascending (csr_degree_order,
+    device): int32 perm, perm[new] = old, for permute()."""
+    L = _lib.load()
+    _dev(A.colind)
+    nb = ctypes.c_size_t()
+    check(L.csr_degree_order_workspace_bytes(A.n, A.nnz, ctypes.byref(nb)), "csr_degree_order")
+    ws = _workspace(nb.value, A.device)
+    perm = torch.empty(max(A.n, 1), dtype=torch.int32, device=A.device)
+    check(L.csr_degree_order(A.n, A.nnz, _ptr(A.colind), _ptr(perm), _ptr(ws), nb.value, _stream()),
+          "csr_degree_order")
+    return perm[:A.n]
+
+
 def permute(A: CSR, perm: torch.Tensor) -> CSR:
     """P A P^T for a device permutation perm[new] = old (csr_permute; FP64 values)."""
     L = _lib.load()

@@ -75,3 +75,34 @@ def test_permute_identity_and_errors(spx, torch):
         spx.permute(G, dup)
     with pytest.raises(ValueError):
         spx.permute(G, ident[:-1].contiguous())
+
+
+@pytest.mark.parametrize("name", ["powerlaw", "stencil5", "empty_cols", "empty"])
+def test_degree_order_bit_exact_and_products(spx, torch, name):
+    """csr_degree_order equals the oracle's order exactly (ties included);
+    the symmetric relabelling it drives keeps (P A P^T)(P x) = P (A x)."""
+    if name == "powerlaw":
+        coo = spgen.powerlaw(30_000, 30_000, 2.0, 6_000, 16.0, 9)
+    elif name == "stencil5":
+        coo = spgen.stencil5(90, 70, 2)
+    elif name == "empty_cols":  # only even columns used
+        rng = np.random.default_rng(3)
+        r = rng.integers(0, 500, 3000).astype(np.int32)
+        c = (2 * rng.integers(0, 250, 3000)).astype(np.int32)
+        coo = spgen.COO(500, 500, r, c, np.ones(3000), {})
+    else:
+        coo = spgen.COO(0, 0, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), {})
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = to_gpu(A)
+    perm = spx.degree_order(G)
+    ph = perm.cpu().numpy()
+    assert np.array_equal(ph, oracle.degree_order(A))
+    if A.m == 0:
+        return
+    Ai = int_valued(A, 11)
+    Bi = spx.permute(to_gpu(Ai), perm)
+    x = spgen.small_ints(A.n, 12)
+    y = oracle.spmv(Ai, x)
+    yp = spx.spmv(Bi, torch.from_numpy(x[ph]).to("cuda:0"),
+                  plan=spx.Plan.for_matrix(Bi, spx.default_opts(1))).cpu().numpy()
+    assert np.array_equal(yp, y[ph])

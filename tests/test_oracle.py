@@ -467,6 +467,30 @@ def test_rcm_components_contiguous():
     assert bandwidth(oracle.permute(A, perm)) == 1
 
 
+def test_degree_order_pins():
+    """Hand-worked case, then invariants: a permutation whose counts never
+    increase, equal counts in ascending index, and the identity when every
+    column has the same count."""
+    # columns used 2, 0, 3, 2, 1 times
+    r = np.array([0, 0, 1, 1, 2, 2, 3, 3], dtype=np.int32)
+    c = np.array([0, 2, 2, 3, 0, 4, 2, 3], dtype=np.int32)
+    A = oracle.csr_from_coo(4, 5, r, c, np.ones(8))
+    assert np.array_equal(oracle.degree_order(A), [2, 0, 3, 4, 1])
+    rng = np.random.default_rng(41)
+    for n, nnz in [(1, 0), (9, 30), (200, 1500)]:
+        rr, cc, vv = rand_coo(rng, n, n, nnz)
+        B = oracle.csr_from_coo(n, n, rr, cc, vv)
+        perm = oracle.degree_order(B)
+        cnt = np.bincount(B.colind, minlength=n)
+        assert np.array_equal(np.sort(perm), np.arange(n))
+        seq = cnt[perm]
+        assert (np.diff(seq) <= 0).all()
+        same = np.diff(seq) == 0
+        assert (np.diff(perm)[same] > 0).all()
+    I = oracle.csr_from_coo(6, 6, np.arange(6, dtype=np.int32), np.arange(6, dtype=np.int32), np.ones(6))
+    assert np.array_equal(oracle.degree_order(I), np.arange(6))
+
+
 def test_vector_access_brute_force_and_closed_forms():
     rng = np.random.default_rng(41)
     for m, n, nnz, line, parts, chunk in [(50, 70, 300, 4, 3, 5), (200, 130, 900, 16, 8, 7), (10, 10, 0, 4, 2, 3)]:
