@@ -25,6 +25,10 @@
  *    within a row for SpMV/SpMM; csr_from_coo produces sorted columns.
  *  - Outputs are overwritten (beta = 0).  An empty row gives +0.0.  m == 0 is a
  *    no-op returning SPX_OK.
+ *  - Sizes: nonzero positions are int32, and the kernels look up to 2^24
+ *    positions past a row's end before comparing, so every call that takes
+ *    nnz (or nnz_in) rejects nnz > SPX_MAX_NNZ = 2^31 - 2^25 with
+ *    SPX_ERR_UNSUPPORTED, and plans reject split_chunk > SPX_MAX_SPLIT_CHUNK.
  *  - Floating point: FP64 values use FP64 arithmetic throughout.  FP32/BF16
  *    values with FP32 x/y accumulate in FP32; rows longer than the plan's
  *    kahan_len use compensated accumulation and an FP64 cross-lane reduction.
@@ -47,6 +51,9 @@ typedef enum {
   SPX_ERR_WORKSPACE = 3,   /* workspace missing or too small */
   SPX_ERR_HIP = 4          /* a HIP runtime call or launch failed */
 } spx_status;
+
+#define SPX_MAX_NNZ 2113929216       /* 2^31 - 2^25 */
+#define SPX_MAX_SPLIT_CHUNK 16777216 /* 2^24 */
 
 typedef enum {
   SPX_F64 = 0,
@@ -79,7 +86,7 @@ typedef struct spx_plan_opts {
   int32_t nbins;
   int32_t upper[SPX_MAX_BINS];
   int32_t lanes[SPX_MAX_BINS];
-  int32_t split_chunk; /* >= 256; nonzeros per segment of a split row */
+  int32_t split_chunk; /* 256 .. SPX_MAX_SPLIT_CHUNK; nonzeros per segment of a split row */
   int32_t kahan_len;   /* FP32 accumulation: rows with L > kahan_len are compensated */
   int32_t max_k;       /* widest SpMM right-hand side the plan serves (>= 1) */
   uint32_t flags;      /* SPX_FLAG_* */
@@ -112,7 +119,7 @@ spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan_opts *opts
  * v: f64[nnz_in].  Outputs rowptr int32[m+1], colind int32[nnz_in] and values
  * f64[nnz_in] (capacity nnz_in); *nnz_out (device int32) receives the stored
  * count, or -1 if some triplet is out of range (then the other outputs are
- * unspecified).  Requires nnz_in < 2^31.  Workspace: csr_from_coo_workspace_bytes. */
+ * unspecified).  Requires nnz_in <= SPX_MAX_NNZ.  Workspace: csr_from_coo_workspace_bytes. */
 spx_status csr_from_coo_workspace_bytes(int32_t m, int32_t n, int64_t nnz_in, size_t *bytes);
 spx_status csr_from_coo(int32_t m, int32_t n, int64_t nnz_in, const int32_t *r, const int32_t *c,
                         const double *v, int32_t *rowptr, int32_t *colind, double *values,

@@ -68,6 +68,10 @@ spx_status product(const char* who, int32_t m, int32_t n, int32_t nnz, const int
                    int32_t k, const void* X, int64_t ldx, void* Y, int64_t ldy, spx_dtype xt,
                    const spx_plan* plan, void* stream) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "%s: negative size", who);
+  {
+    const spx_status s_nnz = check_nnz(nnz, who);
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (k < 1) return fail(SPX_ERR_INVALID, "%s: k=%d < 1", who, k);
   if (ldx < k || ldy < k)
     return fail(SPX_ERR_INVALID, "%s: ldx=%lld / ldy=%lld smaller than k=%d", who, (long long)ldx,
@@ -138,6 +142,10 @@ extern "C" spx_status csr_spmv_t(int32_t m, int32_t n, int32_t nnz, const int32_
   }
   if (mode != 1) return fail(SPX_ERR_INVALID, "csr_spmv_t: mode=%d (0 or 1)", mode);
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_spmv_t: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_spmv_t");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (k < 1) return fail(SPX_ERR_INVALID, "csr_spmv_t: k=%d < 1", k);
   if (k > 1 && (lddy < k || lddx < k)) return fail(SPX_ERR_INVALID, "csr_spmv_t: leading dims < k");
   if (!pair_ok(vtype, xytype)) return fail(SPX_ERR_UNSUPPORTED, "csr_spmv_t: dtype pair");
@@ -165,6 +173,10 @@ extern "C" spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t
                                 const void* X, int64_t ldx, void* out, spx_dtype dtype,
                                 const spx_plan* plan, void* stream) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_sddmm: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_sddmm");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (k < 1) return fail(SPX_ERR_INVALID, "csr_sddmm: k=%d < 1", k);
   if (k > 1 && (lddy < k || ldx < k)) return fail(SPX_ERR_INVALID, "csr_sddmm: leading dims < k");
   if (dtype != SPX_F64 && dtype != SPX_F32)

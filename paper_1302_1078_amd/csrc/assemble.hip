@@ -175,9 +175,13 @@ using namespace spx;
 extern "C" spx_status csr_from_coo_workspace_bytes(int32_t m, int32_t n, int64_t nnz_in,
                                                    size_t* bytes) {
   if (!bytes) return fail(SPX_ERR_INVALID, "csr_from_coo_workspace_bytes: bytes is null");
-  if (m < 0 || n < 0 || nnz_in < 0 || nnz_in >= (int64_t(1) << 31))
+  if (m < 0 || n < 0 || nnz_in < 0)
     return fail(SPX_ERR_INVALID, "csr_from_coo_workspace_bytes: bad sizes m=%d n=%d nnz=%lld", m, n,
                 (long long)nnz_in);
+  {
+    const spx_status s_nnz = check_nnz(nnz_in, "csr_from_coo_workspace_bytes");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   carve_coo(nullptr, nnz_in, bytes);
   return SPX_OK;
 }
@@ -186,8 +190,12 @@ extern "C" spx_status csr_from_coo(int32_t m, int32_t n, int64_t nnz_in, const i
                                    const int32_t* c, const double* v, int32_t* rowptr,
                                    int32_t* colind, double* values, int32_t* nnz_out,
                                    void* workspace, size_t ws_bytes, void* stream) {
-  if (m < 0 || n < 0 || nnz_in < 0 || nnz_in >= (int64_t(1) << 31))
+  if (m < 0 || n < 0 || nnz_in < 0)
     return fail(SPX_ERR_INVALID, "csr_from_coo: bad sizes m=%d n=%d nnz=%lld", m, n, (long long)nnz_in);
+  {
+    const spx_status s_nnz = check_nnz(nnz_in, "csr_from_coo");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (!rowptr || !nnz_out) return fail(SPX_ERR_INVALID, "csr_from_coo: null rowptr or nnz_out");
   if (nnz_in > 0 && (!r || !c || !v || !colind || !values))
     return fail(SPX_ERR_INVALID, "csr_from_coo: null triplet or output array");
@@ -230,6 +238,10 @@ extern "C" spx_status csr_validate(int32_t m, int32_t n, int32_t nnz, const int3
                                    const int32_t* colind, int32_t check_sorted,
                                    int32_t* status_out, void* stream) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_validate: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_validate");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (!rowptr || !status_out || (nnz > 0 && !colind))
     return fail(SPX_ERR_INVALID, "csr_validate: null pointer");
   hipStream_t st = as_stream(stream);
@@ -260,6 +272,10 @@ extern "C" spx_status csr_transpose_index(int32_t m, int32_t n, int32_t nnz, con
                                           int32_t* perm, void* workspace, size_t ws_bytes,
                                           void* stream) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_transpose_index: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_transpose_index");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (!colptr || (nnz > 0 && (!rowptr || !colind || !rowind || !perm)))
     return fail(SPX_ERR_INVALID, "csr_transpose_index: null pointer");
   if (!workspace || ws_bytes < transpose_ws(nnz))

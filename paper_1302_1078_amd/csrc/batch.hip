@@ -204,6 +204,8 @@ spx_status layout_ws(int32_t count, const spx_csr_desc* descs, BatchLayout* L) {
 spx_status check_desc(const spx_csr_desc& d, int i, spx_dtype vt, spx_dtype xt) {
   if (d.m < 0 || d.n < 0 || d.nnz < 0 || d.k < 1)
     return fail(SPX_ERR_INVALID, "batch matrix %d: bad sizes", i);
+  if (d.nnz > SPX_MAX_NNZ)
+    return fail(SPX_ERR_UNSUPPORTED, "batch matrix %d: nnz=%d above SPX_MAX_NNZ", i, d.nnz);
   if (d.vtype != vt || d.xytype != xt)
     return fail(SPX_ERR_UNSUPPORTED, "batch matrix %d: all matrices must share one dtype pair", i);
   if (d.ldx < d.k || d.ldy < d.k) return fail(SPX_ERR_INVALID, "batch matrix %d: ld < k", i);

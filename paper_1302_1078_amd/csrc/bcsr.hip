@@ -281,6 +281,10 @@ extern "C" spx_status csr_bcsr_count(int32_t m, int32_t n, int32_t nnz, const in
                                      const int32_t* colind, int32_t a, int32_t b, int32_t* nblocks_out,
                                      void* workspace, size_t ws_bytes, void* stream) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_bcsr_count: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_bcsr_count");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (!shape_ok(a, b)) return fail(SPX_ERR_UNSUPPORTED, "csr_bcsr_count: block %dx%d (a, b in {1,2,4,8})", a, b);
   if (!nblocks_out || !rowptr || (nnz > 0 && !colind)) return fail(SPX_ERR_INVALID, "csr_bcsr_count: null pointer");
   size_t need = 0;
@@ -306,6 +310,10 @@ extern "C" spx_status csr_to_bcsr(int32_t m, int32_t n, int32_t nnz, const int32
                                   int32_t* bcol, double* bvals, uint64_t* bmask, int32_t* boff, void* workspace,
                                   size_t ws_bytes, void* stream) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_to_bcsr: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_to_bcsr");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (!shape_ok(a, b)) return fail(SPX_ERR_UNSUPPORTED, "csr_to_bcsr: block %dx%d (a, b in {1,2,4,8})", a, b);
   if (!rowptr || !browptr || (nnz > 0 && (!colind || !values || !bcol || !bvals)) ||
       (bitmap && nnz > 0 && (!bmask || !boff)))

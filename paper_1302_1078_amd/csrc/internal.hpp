@@ -30,6 +30,18 @@ spx_status hip_fail(hipError_t e, const char* what);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// nnz within the int32 position range the kernels assume: a position plus
+// one split chunk plus the widest look-ahead past a row's end (U x S <= 2,048
+// slots) stays below 2^31.
+static_assert(static_cast<int64_t>(SPX_MAX_NNZ) + SPX_MAX_SPLIT_CHUNK + 4096 <= 0x7fffffffLL,
+              "position headroom");
+inline spx_status check_nnz(int64_t nnz, const char* who) {
+  if (nnz > SPX_MAX_NNZ)
+    return fail(SPX_ERR_UNSUPPORTED, "%s: nnz=%lld above SPX_MAX_NNZ=%d", who, static_cast<long long>(nnz),
+                SPX_MAX_NNZ);
+  return SPX_OK;
+}
+
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Bump allocator over a caller workspace (256-byte aligned pieces).

@@ -187,8 +187,8 @@ spx_status check_opts(const spx_plan_opts* o) {
       return fail(SPX_ERR_INVALID, "lanes[%d]=0 (split) allowed only for the last bin", b);
     if (l != 0 && !lanes_valid(l)) return fail(SPX_ERR_INVALID, "lanes[%d]=%d not supported", b, l);
   }
-  if (has_split(*o) && o->split_chunk < 256)
-    return fail(SPX_ERR_INVALID, "split_chunk=%d < 256", o->split_chunk);
+  if (has_split(*o) && (o->split_chunk < 256 || o->split_chunk > SPX_MAX_SPLIT_CHUNK))
+    return fail(SPX_ERR_INVALID, "split_chunk=%d outside [256, %d]", o->split_chunk, SPX_MAX_SPLIT_CHUNK);
   if (o->kahan_len < 0) return fail(SPX_ERR_INVALID, "kahan_len < 0");
   if (o->max_k < 1) return fail(SPX_ERR_INVALID, "max_k < 1");
   if (o->occupancy < 0 || o->occupancy > 8)
@@ -246,6 +246,10 @@ extern "C" spx_status csr_plan_workspace_bytes(int32_t m, int32_t nnz, const spx
                                                size_t* bytes) {
   if (!bytes) return fail(SPX_ERR_INVALID, "csr_plan_workspace_bytes: bytes is null");
   if (m < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_plan_workspace_bytes: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_plan_workspace_bytes");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   spx_status s = check_opts(opts);
   if (s != SPX_OK) return s;
   carve_plan(nullptr, m, nnz, *opts, bytes);
@@ -258,6 +262,10 @@ extern "C" spx_status csr_plan_create(int32_t m, int32_t n, int32_t nnz, const i
   if (!out) return fail(SPX_ERR_INVALID, "csr_plan_create: out is null");
   *out = nullptr;
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_plan_create: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_plan_create");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (!rowptr) return fail(SPX_ERR_INVALID, "csr_plan_create: rowptr is null");
   spx_status s = check_opts(opts);
   if (s != SPX_OK) return s;

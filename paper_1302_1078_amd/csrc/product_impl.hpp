@@ -33,6 +33,8 @@ struct Cfg {
   // their lines (see ld_mat)
   static constexpr bool kNT = (KL_ * VEC_ == 1);
   static constexpr int U = (KL_ * VEC_ == 1) ? kUnroll : SPX_UNROLL_MM;
+  // look-ahead past a row's end is at most U x 256 slots (SPX_MAX_NNZ headroom)
+  static_assert(U >= 1 && U * kWG <= 4096, "unroll depth");
 };
 
 template <typename T, int N>

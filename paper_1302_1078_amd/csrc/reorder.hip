@@ -100,6 +100,10 @@ using namespace spx;
 extern "C" spx_status csr_rcm(int32_t m, int32_t n, int32_t nnz, const int32_t* host_rowptr,
                               const int32_t* host_colind, int32_t* host_perm) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_rcm: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_rcm");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (m != n) return fail(SPX_ERR_INVALID, "csr_rcm: the matrix must be square (m=%d, n=%d)", m, n);
   if (m == 0) return SPX_OK;
   if (!host_rowptr || !host_perm || (nnz > 0 && !host_colind))
@@ -282,6 +286,10 @@ extern "C" spx_status csr_degree_order_workspace_bytes(int32_t n, int32_t nnz, s
 extern "C" spx_status csr_degree_order(int32_t n, int32_t nnz, const int32_t* colind, int32_t* perm,
                                        void* workspace, size_t ws_bytes, void* stream) {
   if (n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_degree_order: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_degree_order");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if ((n > 0 && !perm) || (nnz > 0 && !colind)) return fail(SPX_ERR_INVALID, "csr_degree_order: null pointer");
   size_t need = 0;
   spx_status s = csr_degree_order_workspace_bytes(n, nnz, &need);
@@ -321,6 +329,10 @@ extern "C" spx_status csr_permute(int32_t m, int32_t nnz, const int32_t* rowptr,
                                   int32_t* colind_out, double* values_out, int32_t* nnz_out, void* workspace,
                                   size_t ws_bytes, void* stream) {
   if (m < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_permute: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_permute");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
   if (!rowptr || !rowptr_out || !nnz_out || (m > 0 && !perm) ||
       (nnz > 0 && (!colind || !values || !colind_out || !values_out)))
     return fail(SPX_ERR_INVALID, "csr_permute: null pointer");

@@ -107,3 +107,41 @@ def test_plan_opts_roundtrip_and_autotune_cache(tmp_path):
     assert autotune._valid({"opts": {"nbins": 2, "upper": [3], "lanes": [1]}}) is None
     assert autotune._valid({"opts": d}) is not None
     assert autotune._valid({"nope": 1}) is None
+
+
+def test_size_limits_checked_before_any_work(lib):
+    """nnz above SPX_MAX_NNZ is refused as unsupported by every entry point
+    that takes it, before any pointer is read (the kernels' int32 positions
+    need the headroom); split_chunk above SPX_MAX_SPLIT_CHUNK is invalid."""
+    from paper_1302_1078_amd import _lib
+    big = 2**31 - 2**25 + 1
+    null = ctypes.c_void_p(0)
+    sz = ctypes.c_size_t()
+    out = ctypes.c_void_p()
+    o = _lib.PlanOpts.from_dict({"nbins": 2, "upper": [64], "lanes": [64, 0], "split_chunk": 4096, "max_k": 1})
+    unsupported = 2
+    calls = {
+        "csr_spmv": lambda n: lib.csr_spmv(10, 10, n, null, null, null, 0, null, null, 0, null, null),
+        "csr_spmm": lambda n: lib.csr_spmm(10, 10, n, null, null, null, 0, 4, null, 4, null, 4, 0, null, null),
+        "csr_spmv_t": lambda n: lib.csr_spmv_t(10, 10, n, null, null, null, null, null, null, 0, 1, null, 1,
+                                               null, 1, 0, 1, null, null),
+        "csr_sddmm": lambda n: lib.csr_sddmm(10, 10, n, null, null, 1, null, 1, null, 1, null, 0, null, null),
+        "csr_from_coo_workspace_bytes": lambda n: lib.csr_from_coo_workspace_bytes(10, 10, n, ctypes.byref(sz)),
+        "csr_validate": lambda n: lib.csr_validate(10, 10, n, null, null, 0, null, null),
+        "csr_transpose_index": lambda n: lib.csr_transpose_index(10, 10, n, null, null, null, null, null, null,
+                                                                 0, null),
+        "csr_plan_workspace_bytes": lambda n: lib.csr_plan_workspace_bytes(10, n, ctypes.byref(o), ctypes.byref(sz)),
+        "csr_plan_create": lambda n: lib.csr_plan_create(10, 10, n, null, ctypes.byref(o), null, 0, null,
+                                                         ctypes.byref(out)),
+        "csr_degree_order": lambda n: lib.csr_degree_order(10, n, null, null, null, 0, null),
+        "csr_permute": lambda n: lib.csr_permute(10, n, null, null, null, null, null, null, null, null, null, 0,
+                                                 null),
+    }
+    for name, call in calls.items():
+        assert call(big) == unsupported, name
+        assert b"SPX_MAX_NNZ" in lib.spx_last_error(), name
+    o.split_chunk = 2**24 + 1
+    assert lib.csr_plan_workspace_bytes(10, 100, ctypes.byref(o), ctypes.byref(sz)) == 1
+    assert b"split_chunk" in lib.spx_last_error()
+    o.split_chunk = 2**24
+    assert lib.csr_plan_workspace_bytes(10, 100, ctypes.byref(o), ctypes.byref(sz)) == 0
