@@ -182,9 +182,12 @@ spx_status csr_transpose_index(int32_t m, int32_t n, int32_t nnz, const int32_t 
                                int32_t *perm, void *workspace, size_t ws_bytes, void *stream);
 
 /* dX <- A^T dY.  dY is m x k (lddy), dX is n x k (lddx), row-major.
- * mode 0 (CSC index, deterministic): needs colptr/rowind/perm from
+ * mode 0 (CSC index, deterministic): needs colptr/rowind from
  * csr_transpose_index; every column is a gather in ascending row order, run
- * by the product kernels over the CSC pattern (values read through perm).
+ * by the product kernels over the CSC pattern.  With perm (from the same
+ * call) the CSR-order values are read through it; with perm == NULL,
+ * `values` must already be in CSC order (csr_values_to_csc), and the result
+ * is bitwise the same.
  * `plan` (nullable) must then be a plan of the CSC pattern: created from
  * colptr with n rows.  mode 1 (atomic scatter): colptr/rowind/perm may be
  * NULL; dX is zeroed and then accumulated with atomic adds (summation order
@@ -195,6 +198,21 @@ spx_status csr_spmv_t(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, 
                       const void *values, spx_dtype vtype, int32_t k, const void *dY, int64_t lddy,
                       void *dX, int64_t lddx, spx_dtype xytype, int32_t mode, const spx_plan *plan,
                       void *stream);
+
+/* Values in CSC order, values_csc[q] = values[perm[q]] (perm from
+ * csr_transpose_index), moved without per-element random reads: a one-time
+ * map of the pattern (csr_csc_value_map: dest int32[nnz], local
+ * uint16[nnz]) groups the nonzeros by block of SPX_CSC_BLOCK CSC positions;
+ * csr_values_to_csc then streams values into `staging` (nnz elements of
+ * vtype) block by block and reorders each block in LDS into values_csc.
+ * Bitwise a permutation of the input.  Workspace of the map:
+ * csr_csc_value_map_workspace_bytes.  Asynchronous on `stream`. */
+#define SPX_CSC_BLOCK 8192
+spx_status csr_csc_value_map_workspace_bytes(int32_t nnz, size_t *bytes);
+spx_status csr_csc_value_map(int32_t nnz, const int32_t *perm, int32_t *dest, uint16_t *local, void *workspace,
+                             size_t ws_bytes, void *stream);
+spx_status csr_values_to_csc(int32_t nnz, const int32_t *dest, const uint16_t *local, const void *values,
+                             spx_dtype vtype, void *staging, void *values_csc, void *stream);
 
 /* Sampled dot: out[p] = sum_t dY[row(p), t] * X[colind[p], t] for every
  * stored nonzero p (the gradient of y = A(values) x with respect to values).

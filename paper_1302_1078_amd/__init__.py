@@ -5,6 +5,7 @@ the GPU; there is no CPU path, and importing an operation without the built
 library raises.
 """
 from ._lib import PlanOpts, SpxError, missing_symbols  # noqa: F401
-from .ops import (BCSR, CSR, CSCIndex, Plan, bcsr_spmv, default_opts, degree_order, from_coo, permute,  # noqa: F401
+from .ops import (BCSR, CSR, CSCIndex, CSCValueMap, Plan, bcsr_spmv, csc_value_map, default_opts,  # noqa: F401
+                  degree_order, from_coo, permute, values_to_csc,
                   probe, rcm, sddmm, spmm, spmv, spmv_t, transpose_index, ucld, validate, vector_access, version)
 from .autograd import GradContext, SpMVFunction, spmv_autograd  # noqa: F401

@@ -95,6 +95,9 @@ SIGNATURES = {
                                 ctypes.c_int, P, P]),
     "csr_transpose_index_workspace_bytes": (ctypes.c_int, [i32, i32, i32, SZ]),
     "csr_transpose_index": (ctypes.c_int, [i32, i32, i32, P, P, P, P, P, P, ctypes.c_size_t, P]),
+    "csr_csc_value_map_workspace_bytes": (ctypes.c_int, [i32, SZ]),
+    "csr_csc_value_map": (ctypes.c_int, [i32, P, P, P, P, ctypes.c_size_t, P]),
+    "csr_values_to_csc": (ctypes.c_int, [i32, P, P, P, ctypes.c_int, P, P, P]),
     "csr_spmv_t": (ctypes.c_int, [i32, i32, i32, P, P, P, P, P, P, ctypes.c_int, i32, P, i64, P, i64,
                                   ctypes.c_int, i32, P, P]),
     "csr_sddmm": (ctypes.c_int, [i32, i32, i32, P, P, i32, P, i64, P, i64, P, ctypes.c_int, P, P]),

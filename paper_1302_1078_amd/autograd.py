@@ -4,20 +4,25 @@ Forward: csr_spmv / csr_spmm.  Backward (both on the GPU through the C ABI):
   d values[p] = dY[row(p), :] . X[colind[p], :]   (csr_sddmm, sampled dot)
   d X         = A^T dY                            (csr_spmv_t: CSC-index gather,
                                                    or atomic scatter)
+With the CSC index (mode 0) and csc_values, the values are first moved to CSC
+order by the two-pass block transposition (csr_values_to_csc), so the gather
+reads them in sequence instead of through perm; the result is bitwise the
+same.
 y is bilinear in (values, x), so these are the exact gradients.
 """
 from __future__ import annotations
 
 import torch
 
-from .ops import CSR, Plan, default_opts, sddmm, spmm, spmv, spmv_t, transpose_index
+from .ops import (CSCIndex, CSR, Plan, csc_value_map, default_opts, sddmm, spmm, spmv, spmv_t, transpose_index,
+                  values_to_csc)
 
 
 class GradContext:
     """Per-pattern state reused across calls: forward plan, CSC index and the
     plan of the CSC pattern (for the deterministic transpose)."""
 
-    def __init__(self, A: CSR, mode: int = 0, plans: bool = True, k: int = 1):
+    def __init__(self, A: CSR, mode: int = 0, plans: bool = True, k: int = 1, csc_values: bool = True):
         self.A = A
         self.mode = mode
         self.plan = Plan.for_matrix(A, default_opts(k, A.values.dtype)) if plans else None
@@ -25,6 +30,17 @@ class GradContext:
         self.plan_t = None
         if plans and mode == 0:
             self.plan_t = Plan(self.index.colptr, A.n, A.m, A.nnz, default_opts(k, A.values.dtype))
+        self.vmap = csc_value_map(self.index) if (mode == 0 and csc_values) else None
+        self.index_v = CSCIndex(self.index.colptr, self.index.rowind, None) if self.vmap is not None else None
+
+    def transpose(self, A: CSR, dy: torch.Tensor) -> torch.Tensor:
+        """A^T dy by this context's mode."""
+        if self.mode != 0:
+            return spmv_t(A, dy, mode=1, plan=self.plan)
+        if self.vmap is None:
+            return spmv_t(A, dy, mode=0, index=self.index, plan=self.plan_t)
+        vcsc = values_to_csc(A.values, self.vmap)
+        return spmv_t(A.with_values(vcsc), dy, mode=0, index=self.index_v, plan=self.plan_t)
 
 
 class SpMVFunction(torch.autograd.Function):
@@ -46,10 +62,7 @@ class SpMVFunction(torch.autograd.Function):
         if ctx.needs_input_grad[0]:
             dvalues = sddmm(A, dy, x, plan=g.plan)
         if ctx.needs_input_grad[1]:
-            if g.mode == 0:
-                dx = spmv_t(A, dy, mode=0, index=g.index, plan=g.plan_t)
-            else:
-                dx = spmv_t(A, dy, mode=1, plan=g.plan)
+            dx = g.transpose(A, dy)
         return dvalues, dx, None
 
 

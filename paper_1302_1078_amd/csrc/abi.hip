@@ -133,10 +133,11 @@ extern "C" spx_status csr_spmv_t(int32_t m, int32_t n, int32_t nnz, const int32_
                                  int64_t lddx, spx_dtype xytype, int32_t mode,
                                  const spx_plan* plan, void* stream) {
   if (mode == 0) {
-    if (nnz > 0 && (!colptr || !rowind || !perm))
+    if (nnz > 0 && (!colptr || !rowind))
       return fail(SPX_ERR_INVALID, "csr_spmv_t: CSC index arrays are required for mode 0");
     if (n > 0 && !colptr) return fail(SPX_ERR_INVALID, "csr_spmv_t: colptr is null");
-    // gather over the CSC pattern: n "rows", values read through perm
+    // gather over the CSC pattern: n "rows", values read through perm (or,
+    // with perm == NULL, values already in CSC order)
     return product("csr_spmv_t", n, m, nnz, colptr, rowind, values, perm, vtype, k, dY, lddy, dX,
                    lddx, xytype, plan, stream);
   }

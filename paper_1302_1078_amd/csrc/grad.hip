@@ -128,3 +128,170 @@ spx_status launch_sddmm(ProdArgs& a, const spx_plan* plan, int32_t m, int32_t nn
 }
 
 }  // namespace spx
+
+// ------------------------------------------------------------------ values in CSC order
+// values_csc[q] = values[perm[q]] without the random reads of a gather (each
+// would fetch a whole line for 2-8 useful bytes).  A one-time map groups the
+// nonzeros by block of SPX_CSC_BLOCK consecutive CSC positions: dest[p] is
+// p's slot in a staging array whose block b holds, in ascending p, the
+// nonzeros whose CSC position lies in block b, and local[i] is the position
+// inside block b of staging slot i.  Pass 1 streams values and writes each to
+// dest[p]: a workgroup's writes to one block form a contiguous run that its
+// neighbours (same XCD) continue, so lines fill in L2.  Pass 2 reads one block
+// of staging coalesced, reorders it in LDS by local[], and writes it out
+// coalesced.
+namespace spx {
+namespace {
+
+__global__ void k_inv_perm(const int32_t* __restrict__ perm, int32_t nnz, int32_t* __restrict__ pos) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nnz) return;
+  const int32_t p = perm[q];
+  if (p >= 0 && p < nnz) pos[p] = static_cast<int32_t>(q);
+}
+
+__global__ void k_block_keys(const int32_t* __restrict__ pos, int32_t nnz, uint32_t* __restrict__ keys,
+                             int32_t* __restrict__ vals) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  keys[p] = static_cast<uint32_t>(pos[p]) / SPX_CSC_BLOCK;
+  vals[p] = static_cast<int32_t>(p);
+}
+
+// sorted[i] = the nonzero p at staging slot i (stable by p within a block)
+__global__ void k_fill_map(const int32_t* __restrict__ sorted, const int32_t* __restrict__ pos, int32_t nnz,
+                           int32_t* __restrict__ dest, uint16_t* __restrict__ local) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nnz) return;
+  const int32_t p = sorted[i];
+  dest[p] = static_cast<int32_t>(i);
+  local[i] = static_cast<uint16_t>(static_cast<uint32_t>(pos[p]) % SPX_CSC_BLOCK);
+}
+
+// Pass 1 tiles are XCD-contiguous (grid a multiple of 8): XCD j streams one
+// contiguous eighth of the nonzeros, so its part of every block's run is
+// contiguous and the run's lines fill in that XCD's L2 instead of being
+// written piecemeal from all eight.
+constexpr int kStagePerThread = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_to_staging(const T* __restrict__ values, const int32_t* __restrict__ dest,
+                                                    int32_t nnz, T* __restrict__ staging) {
+  const int64_t base = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * (kWG * kStagePerThread);
+  int32_t d[kStagePerThread];
+  T v[kStagePerThread];
+#pragma unroll
+  for (int u = 0; u < kStagePerThread; ++u) {
+    const int64_t p = base + u * kWG + threadIdx.x;
+    d[u] = (p < nnz) ? ld_stream(dest + p) : -1;
+    v[u] = (p < nnz) ? ld_stream(values + p) : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < kStagePerThread; ++u)
+    if (d[u] >= 0 && d[u] < nnz) staging[d[u]] = v[u];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_from_staging(const T* __restrict__ staging,
+                                                      const uint16_t* __restrict__ local, int32_t nnz,
+                                                      T* __restrict__ out) {
+  constexpr int PER = SPX_CSC_BLOCK / kWG;
+  static_assert(SPX_CSC_BLOCK % kWG == 0 && SPX_CSC_BLOCK <= 65536, "block of 16-bit positions");
+  __shared__ T blk[SPX_CSC_BLOCK];
+  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * SPX_CSC_BLOCK;
+  const int64_t left = static_cast<int64_t>(nnz) - b0;
+  const int32_t cnt = static_cast<int32_t>(left < SPX_CSC_BLOCK ? left : SPX_CSC_BLOCK);
+  // all of a thread's loads are issued before the first LDS store
+  uint16_t l[PER];
+  T v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int32_t i = u * kWG + threadIdx.x;
+    l[u] = (i < cnt) ? ld_stream(local + b0 + i) : static_cast<uint16_t>(0xffff);
+    v[u] = (i < cnt) ? ld_stream(staging + b0 + i) : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    if (l[u] < cnt) blk[l[u]] = v[u];
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < cnt; i += kWG) __builtin_nontemporal_store(blk[i], out + b0 + i);
+}
+
+unsigned grid256(int64_t n) { return static_cast<unsigned>((n + 255) / 256); }
+
+int bits_for(int64_t v) {
+  int b = 1;
+  while ((int64_t(1) << b) <= v) ++b;
+  return b;
+}
+
+}  // namespace
+}  // namespace spx
+
+using namespace spx;
+
+extern "C" spx_status csr_csc_value_map_workspace_bytes(int32_t nnz, size_t* bytes) {
+  if (!bytes || nnz < 0) return fail(SPX_ERR_INVALID, "csr_csc_value_map_workspace_bytes: bad argument");
+  const size_t n = static_cast<size_t>(nnz > 0 ? nnz : 1);
+  *bytes = 3 * align_up(n * 4) + radix_workspace_bytes(nnz, 4);
+  return SPX_OK;
+}
+
+extern "C" spx_status csr_csc_value_map(int32_t nnz, const int32_t* perm, int32_t* dest, uint16_t* local,
+                                        void* workspace, size_t ws_bytes, void* stream) {
+  if (nnz < 0) return fail(SPX_ERR_INVALID, "csr_csc_value_map: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_csc_value_map");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
+  if (nnz == 0) return SPX_OK;
+  if (!perm || !dest || !local) return fail(SPX_ERR_INVALID, "csr_csc_value_map: null pointer");
+  size_t need = 0;
+  csr_csc_value_map_workspace_bytes(nnz, &need);
+  if (!workspace || ws_bytes < need)
+    return fail(SPX_ERR_WORKSPACE, "csr_csc_value_map: workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = as_stream(stream);
+  char* w = static_cast<char*>(workspace);
+  const size_t n4 = align_up(static_cast<size_t>(nnz) * 4);
+  int32_t* pos = reinterpret_cast<int32_t*>(w);
+  uint32_t* keys = reinterpret_cast<uint32_t*>(w + n4);
+  int32_t* vals = reinterpret_cast<int32_t*>(w + 2 * n4);
+  void* rws = w + 3 * n4;
+  k_inv_perm<<<grid256(nnz), 256, 0, st>>>(perm, nnz, pos);
+  SPX_LAUNCHED("k_inv_perm");
+  k_block_keys<<<grid256(nnz), 256, 0, st>>>(pos, nnz, keys, vals);
+  SPX_LAUNCHED("k_block_keys");
+  const spx_status s = radix_sort_u32(keys, vals, nnz, bits_for((static_cast<int64_t>(nnz) - 1) / SPX_CSC_BLOCK), rws, st);
+  if (s != SPX_OK) return s;
+  k_fill_map<<<grid256(nnz), 256, 0, st>>>(vals, pos, nnz, dest, local);
+  SPX_LAUNCHED("k_fill_map");
+  return SPX_OK;
+}
+
+extern "C" spx_status csr_values_to_csc(int32_t nnz, const int32_t* dest, const uint16_t* local,
+                                        const void* values, spx_dtype vtype, void* staging, void* values_csc,
+                                        void* stream) {
+  if (nnz < 0) return fail(SPX_ERR_INVALID, "csr_values_to_csc: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_values_to_csc");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
+  if (nnz == 0) return SPX_OK;
+  if (!dest || !local || !values || !staging || !values_csc)
+    return fail(SPX_ERR_INVALID, "csr_values_to_csc: null pointer");
+  hipStream_t st = as_stream(stream);
+  const unsigned nb = static_cast<unsigned>((static_cast<int64_t>(nnz) + SPX_CSC_BLOCK - 1) / SPX_CSC_BLOCK);
+  const int64_t tiles = (static_cast<int64_t>(nnz) + kWG * kStagePerThread - 1) / (kWG * kStagePerThread);
+  const unsigned g1 = static_cast<unsigned>((tiles + 7) / 8 * 8);
+#define SPX_TO_CSC(T)                                                                                    \
+  k_to_staging<T><<<g1, kWG, 0, st>>>(static_cast<const T*>(values), dest, nnz, static_cast<T*>(staging)); \
+  SPX_LAUNCHED("k_to_staging");                                                                          \
+  k_from_staging<T><<<nb, kWG, 0, st>>>(static_cast<const T*>(staging), local, nnz, static_cast<T*>(values_csc)); \
+  SPX_LAUNCHED("k_from_staging");                                                                        \
+  return SPX_OK;
+  if (vtype == SPX_F64) { SPX_TO_CSC(double) }
+  if (vtype == SPX_F32) { SPX_TO_CSC(float) }
+  if (vtype == SPX_BF16) { SPX_TO_CSC(uint16_t) }
+#undef SPX_TO_CSC
+  return fail(SPX_ERR_UNSUPPORTED, "csr_values_to_csc: vtype %d", vtype);
+}

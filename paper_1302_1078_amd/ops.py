@@ -240,10 +240,49 @@ def transpose_index(A: CSR) -> CSCIndex:
     return CSCIndex(colptr, rowind[:A.nnz], perm[:A.nnz])
 
 
+@dataclass
+class CSCValueMap:
+    """One-time map of a pattern for csr_values_to_csc (dest int32[nnz],
+    local uint16[nnz] stored as int16)."""
+    dest: torch.Tensor
+    local: torch.Tensor
+
+
+def csc_value_map(index: CSCIndex) -> CSCValueMap:
+    L = _lib.load()
+    perm = index.perm
+    nnz = perm.numel()
+    nb = ctypes.c_size_t()
+    check(L.csr_csc_value_map_workspace_bytes(nnz, ctypes.byref(nb)), "csr_csc_value_map")
+    ws = _workspace(nb.value, perm.device)
+    dest = torch.empty(max(nnz, 1), dtype=torch.int32, device=perm.device)
+    local = torch.empty(max(nnz, 1), dtype=torch.int16, device=perm.device)
+    check(L.csr_csc_value_map(nnz, _ptr(perm), _ptr(dest), _ptr(local), _ptr(ws), nb.value, _stream()),
+          "csr_csc_value_map")
+    return CSCValueMap(dest[:nnz], local[:nnz])
+
+
+def values_to_csc(values: torch.Tensor, vmap: CSCValueMap, staging: torch.Tensor | None = None,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """values[perm] in CSC order through the two-pass block transposition
+    (csr_values_to_csc)."""
+    _dev(values)
+    _contig(values)
+    nnz = values.numel()
+    if vmap.dest.numel() != nnz:
+        raise ValueError("values_to_csc: map and values differ in size")
+    staging = torch.empty_like(values) if staging is None else staging
+    out = torch.empty_like(values) if out is None else out
+    check(_lib.load().csr_values_to_csc(nnz, _ptr(vmap.dest), _ptr(vmap.local), _ptr(values), dtype_code(values),
+                                        _ptr(staging), _ptr(out), _stream()), "csr_values_to_csc")
+    return out
+
+
 def spmv_t(A: CSR, dY: torch.Tensor, mode: int = 0, index: CSCIndex | None = None,
            plan: Plan | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """dX <- A^T dY.  mode 0: deterministic gather over the CSC index (plan, if
-    given, is a plan of the CSC pattern); mode 1: atomic scatter (plan of the
+    given, is a plan of the CSC pattern; an index whose perm is None means
+    A.values are already in CSC order); mode 1: atomic scatter (plan of the
     CSR pattern)."""
     L = _lib.load()
     _dev(A.rowptr, dY)

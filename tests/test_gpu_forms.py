@@ -166,6 +166,45 @@ def test_spmv_t_parity(spx, torch, kind, k):
     assert np.array_equal(outs[1].view(np.uint64), again.view(np.uint64))  # deterministic
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nnz", [0, 1, 8191, 8192, 3 * 8192 + 77])
+def test_values_to_csc_is_the_permutation(spx, torch, dtype, nnz):
+    """The two-pass block transposition returns values[perm] bit for bit:
+    empty, one element, one block minus one, exactly one block, and several
+    blocks with a ragged last one (perm: a random permutation)."""
+    from paper_1302_1078_amd.ops import CSCIndex
+    rng = np.random.default_rng(nnz)
+    perm = rng.permutation(nnz).astype(np.int32)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    vals = torch.from_numpy(spgen.uniform(max(nnz, 1), 3)[:nnz]).to("cuda:0").to(tdt)
+    pm = dev(torch, perm)
+    vmap = spx.csc_value_map(CSCIndex(None, None, pm))
+    got = spx.values_to_csc(vals, vmap)
+    want = vals[pm.long()]
+    assert torch.equal(got.view(torch.int16) if dtype == "bf16" else got,
+                       want.view(torch.int16) if dtype == "bf16" else want)
+
+
+@pytest.mark.parametrize("kind", ["powerlaw", "wide", "one_long_row"])
+@pytest.mark.parametrize("k", [1, 3])
+def test_spmv_t_csc_values_bitwise(spx, torch, kind, k):
+    """A^T dY with values moved to CSC order (perm = NULL) is bitwise the
+    transpose that reads them through perm, with and without a plan."""
+    from paper_1302_1078_amd.ops import CSCIndex
+    A = matrix(kind, 36)
+    G = to_gpu(A)
+    dY = spgen.normal(A.m * k, 37).reshape(A.m, k)
+    dYd = dev(torch, dY if k > 1 else dY[:, 0])
+    idx = spx.transpose_index(G)
+    vcsc = spx.values_to_csc(G.values, spx.csc_value_map(idx))
+    nop = CSCIndex(idx.colptr, idx.rowind, None)
+    plan_t = spx.Plan(idx.colptr, A.n, A.m, A.nnz, spx.default_opts(k))
+    for pl in (None, plan_t):
+        a = spx.spmv_t(G, dYd, mode=0, index=idx, plan=pl).cpu().numpy()
+        b = spx.spmv_t(G.with_values(vcsc), dYd, mode=0, index=nop, plan=pl).cpu().numpy()
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
 def test_spmv_t_exact_inputs_and_adjoint(spx, torch):
     A = int_valued(matrix("powerlaw", 34), 1)
     G = to_gpu(A)
