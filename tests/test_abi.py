@@ -134,6 +134,8 @@ def test_size_limits_checked_before_any_work(lib):
         "csr_plan_create": lambda n: lib.csr_plan_create(10, 10, n, null, ctypes.byref(o), null, 0, null,
                                                          ctypes.byref(out)),
         "csr_degree_order": lambda n: lib.csr_degree_order(10, n, null, null, null, 0, null),
+        "csr_csc_value_map": lambda n: lib.csr_csc_value_map(n, null, null, null, null, 0, null),
+        "csr_values_to_csc": lambda n: lib.csr_values_to_csc(n, null, null, null, 0, null, null, null),
         "csr_permute": lambda n: lib.csr_permute(10, n, null, null, null, null, null, null, null, null, null, 0,
                                                  null),
     }
