@@ -13,19 +13,60 @@ namespace {
 
 enum { kScatterT = 0, kSddmm = 1 };
 
+// The nonzeros p, p + step, ... < p1 of one row, kVisit at a time: the index
+// (and value) loads of a round are issued before any gather, and the gathers
+// before any use, so a lane keeps kVisit load chains in flight.  Each
+// nonzero's arithmetic is the same expression whatever the batching.
+constexpr int kVisit = 4;
+
 template <typename VT, typename XT, int MODE>
-__device__ __forceinline__ void visit(const ProdArgs& a, int32_t row, int32_t p) {
-  const int32_t c = ld_stream(a.colind + p);
+__device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_t p, int32_t p1, int step) {
   const XT* dy = static_cast<const XT*>(a.X) + static_cast<int64_t>(row) * a.ldx;
-  if constexpr (MODE == kScatterT) {
-    const XT v = static_cast<XT>(ValueLoad<VT>::get(static_cast<const VT*>(a.values) + p));
-    XT* dst = static_cast<XT*>(a.Y) + static_cast<int64_t>(c) * a.ldy;
-    for (int t = 0; t < a.k; ++t) atomicAdd(dst + t, v * dy[t]);
-  } else {
-    const XT* xr = static_cast<const XT*>(a.X2) + static_cast<int64_t>(c) * a.ldx2;
-    XT s = XT(0);
-    for (int t = 0; t < a.k; ++t) s = s + dy[t] * xr[t];
-    __builtin_nontemporal_store(s, static_cast<XT*>(a.Y) + p);
+  const XT dy0 = (p < p1) ? dy[0] : XT(0);  // k = 1: one dY entry per row
+  for (; p < p1; p += kVisit * step) {
+    bool h[kVisit];
+    int32_t c[kVisit];
+#pragma unroll
+    for (int u = 0; u < kVisit; ++u) {
+      h[u] = p + u * step < p1;
+      c[u] = h[u] ? ld_stream(a.colind + p + u * step) : 0;
+    }
+    if constexpr (MODE == kScatterT) {
+      XT v[kVisit];
+#pragma unroll
+      for (int u = 0; u < kVisit; ++u)
+        v[u] = h[u] ? static_cast<XT>(ValueLoad<VT>::get(static_cast<const VT*>(a.values) + p + u * step)) : XT(0);
+#pragma unroll
+      for (int u = 0; u < kVisit; ++u) {
+        if (!h[u]) continue;
+        XT* dst = static_cast<XT*>(a.Y) + static_cast<int64_t>(c[u]) * a.ldy;
+        if (a.k == 1) atomicAdd(dst, v[u] * dy0);
+        else
+          for (int t = 0; t < a.k; ++t) atomicAdd(dst + t, v[u] * dy[t]);
+      }
+    } else {
+      const XT* X2 = static_cast<const XT*>(a.X2);
+      if (a.k == 1) {
+        XT xr[kVisit];
+#pragma unroll
+        for (int u = 0; u < kVisit; ++u) xr[u] = h[u] ? X2[static_cast<int64_t>(c[u]) * a.ldx2] : XT(0);
+#pragma unroll
+        for (int u = 0; u < kVisit; ++u) {
+          XT s = XT(0);
+          s = s + dy0 * xr[u];
+          if (h[u]) __builtin_nontemporal_store(s, static_cast<XT*>(a.Y) + p + u * step);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kVisit; ++u) {
+          if (!h[u]) continue;
+          const XT* xr = X2 + static_cast<int64_t>(c[u]) * a.ldx2;
+          XT s = XT(0);
+          for (int t = 0; t < a.k; ++t) s = s + dy[t] * xr[t];
+          __builtin_nontemporal_store(s, static_cast<XT*>(a.Y) + p + u * step);
+        }
+      }
+    }
   }
 }
 
@@ -46,7 +87,7 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
     const int32_t re = a.rowptr[row + 1];
     const int32_t p0 = a.rowptr[row] + (tile - f) * a.chunk;
     const int32_t p1 = min(p0 + a.chunk, re);
-    for (int32_t p = p0 + t; p < p1; p += kWG) visit<VT, XT, MODE>(a, row, p);
+    visit_run<VT, XT, MODE>(a, row, p0 + t, p1, kWG);
     return;
   }
   // row groups of G lanes; a bin may give each group several rows (rpg),
@@ -57,13 +98,25 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
   const int G = stream ? 8 : d.lanes;
   const int rpg = stream ? 8 : d.rpg;  // 32 groups x 8 rows = the bin's 256 rows per workgroup
   const int ng = kWG / G;
-  for (int j = 0; j < rpg; ++j) {
+  // every row id and range of the group first (independent loads), then the rows
+  constexpr int kMaxRpg = 8;
+  int32_t rows[kMaxRpg], q0[kMaxRpg], q1[kMaxRpg];
+#pragma unroll
+  for (int j = 0; j < kMaxRpg; ++j) {
     const int idx = (tile * rpg + j) * ng + t / G;
-    if (idx >= d.nrows) continue;
-    const int32_t row = a.row_perm ? a.row_perm[d.row_begin + idx] : d.row_begin + idx;
-    const int32_t p1 = a.rowptr[row + 1];
-    for (int32_t p = a.rowptr[row] + t % G; p < p1; p += G) visit<VT, XT, MODE>(a, row, p);
+    rows[j] = -1;
+    q0[j] = q1[j] = 0;
+    if (j < rpg && idx < d.nrows) rows[j] = a.row_perm ? a.row_perm[d.row_begin + idx] : d.row_begin + idx;
   }
+#pragma unroll
+  for (int j = 0; j < kMaxRpg; ++j) {
+    if (rows[j] < 0) continue;
+    q0[j] = a.rowptr[rows[j]];
+    q1[j] = a.rowptr[rows[j] + 1];
+  }
+#pragma unroll
+  for (int j = 0; j < kMaxRpg; ++j)
+    if (rows[j] >= 0) visit_run<VT, XT, MODE>(a, rows[j], q0[j] + t % G, q1[j], G);
 }
 
 template <typename XT>
