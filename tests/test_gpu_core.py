@@ -431,3 +431,65 @@ def test_nan_inf_stay_in_their_rows(spx, torch, k):
         Y = spx.spmm(G, Xd, plan=plan) if k > 1 else spx.spmv(G, Xd, plan=plan)
         Y = Y.cpu().numpy().reshape(A.m, k)
         assert np.array_equal(Y, ref, equal_nan=True), name
+
+
+def test_products_graph_replay(spx, torch):
+    """Single products captured in one HIP graph (SpMV with split rows, SpMM,
+    values to CSC order, the CSC transpose, the sampled dot) give on every
+    replay, with new inputs written eagerly between replays, bitwise the
+    results of the same calls made eagerly."""
+    from paper_1302_1078_amd.ops import CSCIndex
+    A = matrix("one_long_row", 41)
+    G = to_gpu(A)
+    dev = "cuda:0"
+    k = 16
+    plan_v = spx.Plan.for_matrix(G, spx.default_opts(1))
+    assert plan_v.info()["segments"] > 1  # the 50,000-entry row is cut into split segments
+    plan_m = spx.Plan.for_matrix(G, spx.default_opts(k))
+    idx = spx.transpose_index(G)
+    vmap = spx.csc_value_map(idx)
+    nop = CSCIndex(idx.colptr, idx.rowind, None)
+    plan_t = spx.Plan(idx.colptr, A.n, A.m, A.nnz, spx.default_opts(1))
+    x = torch.empty(A.n, dtype=torch.float64, device=dev)
+    X = torch.empty((A.n, k), dtype=torch.float64, device=dev)
+    dy = torch.empty(A.m, dtype=torch.float64, device=dev)
+    y = torch.empty(A.m, dtype=torch.float64, device=dev)
+    Y = torch.empty((A.m, k), dtype=torch.float64, device=dev)
+    stage = torch.empty_like(G.values)
+    vcsc = torch.empty_like(G.values)
+    dx = torch.empty(A.n, dtype=torch.float64, device=dev)
+    dv = torch.empty(A.nnz, dtype=torch.float64, device=dev)
+    Gc = G.with_values(vcsc)
+
+    def calls():
+        spx.spmv(G, x, y=y, plan=plan_v)
+        spx.spmm(G, X, Y=Y, plan=plan_m)
+        spx.values_to_csc(G.values, vmap, staging=stage, out=vcsc)
+        spx.spmv_t(Gc, dy, mode=0, index=nop, plan=plan_t, out=dx)
+        spx.sddmm(G, dy, x, out=dv)
+
+    outs = (y, Y, vcsc, dx, dv)
+    for t_ in (x, X, dy):
+        t_.uniform_(-1.0, 1.0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        calls()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        calls()
+    for rep in range(3):
+        for t_ in (x, X, dy):
+            t_.uniform_(-1.0, 1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [t_.clone() for t_ in outs]
+        calls()
+        torch.cuda.synchronize()
+        for name, a, b in zip(("spmv", "spmm", "values_to_csc", "spmv_t", "sddmm"), got, outs):
+            assert torch.equal(a, b), (rep, name)
+    ref = oracle.spmv(A, x.cpu().numpy())
+    assert oracle.rel2(y.cpu().numpy(), ref) <= TOL_F64
