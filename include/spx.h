@@ -142,7 +142,12 @@ spx_status csr_validate(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr
  * caller's workspace, which must stay allocated and unmodified while the plan
  * is used.  csr_plan_create reads the device rowptr and SYNCHRONISES `stream`
  * (it copies the bin sizes back to the host).  The plan may be used with any
- * values/x/X of the same pattern; SpMM with the plan needs k <= opts.max_k. */
+ * values/x/X of the same pattern; SpMM with the plan needs k <= opts.max_k.
+ * A plan with split rows keeps per-row arrival counters and partial sums in
+ * its workspace: products through one such plan must not run concurrently
+ * (order them on one stream, or give each stream its own plan); calls in
+ * sequence are fine, since the last segment of each row resets its counter.
+ * The same holds for a batch and its workspace. */
 spx_status csr_plan_workspace_bytes(int32_t m, int32_t nnz, const spx_plan_opts *opts, size_t *bytes);
 spx_status csr_plan_create(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr,
                            const spx_plan_opts *opts, void *workspace, size_t ws_bytes,
