@@ -70,6 +70,100 @@ __device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_
   }
 }
 
+// Stream bin, k = 1: the tile's 256 rows (one per thread) are walked as one
+// flat sequence of nonzeros, as the forward stream kernel does: lanes take
+// consecutive nonzeros (coalesced index loads and output stores), the row of
+// each comes from a lockstep search over the rows' offsets in LDS, and the
+// rows' dY entries are staged in LDS once.
+template <typename VT, typename XT, int MODE>
+__device__ __forceinline__ void visit_stream(const ProdArgs& a, const BinDesc& d, int tile) {
+  constexpr int kStreamRows = kWG;  // a stream tile: one bin row per thread (the bin table's layout)
+  constexpr int kChunk = 1024, kPer = kChunk / kWG;
+  __shared__ int32_t s_off[kStreamRows + 1];
+  __shared__ int32_t s_p0[kStreamRows];
+  __shared__ XT s_dy[kStreamRows];
+  __shared__ int32_t s_wsum[kWG / kWave];
+  if (tile * kStreamRows >= d.nrows) return;
+  const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+  const int idx = tile * kStreamRows + t;
+  int32_t row = 0, p0 = 0, p1 = 0;
+  if (idx < d.nrows) {
+    if (a.row_perm) {
+      row = a.row_perm[d.row_begin + idx];
+      const int2 pr = reinterpret_cast<const int2*>(a.prange)[d.row_begin + idx];
+      p0 = pr.x;
+      p1 = pr.y;
+    } else {
+      row = d.row_begin + idx;
+      p0 = a.rowptr[row];
+      p1 = a.rowptr[row + 1];
+    }
+  }
+  const int32_t L = p1 - p0;
+  const XT dyv = (L > 0) ? static_cast<const XT*>(a.X)[static_cast<int64_t>(row) * a.ldx] : XT(0);
+  int32_t inc = L;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t u = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += u;
+  }
+  if (lane == kWave - 1) s_wsum[w] = inc;
+  __syncthreads();
+  int32_t before = 0, total = 0;
+#pragma unroll
+  for (int i = 0; i < kWG / kWave; ++i) {
+    if (i < w) before += s_wsum[i];
+    total += s_wsum[i];
+  }
+  s_off[t] = before + inc - L;
+  s_p0[t] = p0;
+  s_dy[t] = dyv;
+  if (t == kWG - 1) s_off[kStreamRows] = total;
+  total = __builtin_amdgcn_readfirstlane(total);
+  __syncthreads();
+  for (int32_t base = 0; base < total; base += kChunk) {
+    int32_t lo[kPer], p[kPer], c[kPer];
+    bool ok[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int32_t j = base + u * kWG + t;
+      ok[u] = j < total;
+      lo[u] = 0;
+      p[u] = ok[u] ? j : total - 1;  // the search key; past the end: the last element again
+    }
+#pragma unroll
+    for (int step = kStreamRows / 2; step >= 1; step >>= 1) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u)
+        if (s_off[lo[u] + step] <= p[u]) lo[u] += step;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      p[u] = s_p0[lo[u]] + (p[u] - s_off[lo[u]]);
+      c[u] = ld_stream(a.colind + p[u]);
+    }
+    if constexpr (MODE == kScatterT) {
+      XT v[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u)
+        v[u] = static_cast<XT>(ValueLoad<VT>::get(static_cast<const VT*>(a.values) + p[u]));
+#pragma unroll
+      for (int u = 0; u < kPer; ++u)
+        if (ok[u]) atomicAdd(static_cast<XT*>(a.Y) + static_cast<int64_t>(c[u]) * a.ldy, v[u] * s_dy[lo[u]]);
+    } else {
+      XT xr[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) xr[u] = static_cast<const XT*>(a.X2)[static_cast<int64_t>(c[u]) * a.ldx2];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        XT s = XT(0);
+        s = s + s_dy[lo[u]] * xr[u];
+        if (ok[u]) __builtin_nontemporal_store(s, static_cast<XT*>(a.Y) + p[u]);
+      }
+    }
+  }
+}
+
 template <typename VT, typename XT, int MODE>
 __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
   const int b = blockIdx.x;
@@ -88,6 +182,10 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
     const int32_t p0 = a.rowptr[row] + (tile - f) * a.chunk;
     const int32_t p1 = min(p0 + a.chunk, re);
     visit_run<VT, XT, MODE>(a, row, p0 + t, p1, kWG);
+    return;
+  }
+  if (d.lanes == SPX_LANES_STREAM && a.k == 1) {
+    visit_stream<VT, XT, MODE>(a, d, tile);
     return;
   }
   // row groups of G lanes; a bin may give each group several rows (rpg),
