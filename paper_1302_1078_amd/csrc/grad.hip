@@ -342,6 +342,93 @@ __global__ __launch_bounds__(kWG) void k_to_staging(const T* __restrict__ values
     if (d[u] >= 0 && d[u] < nnz) staging[d[u]] = v[u];
 }
 
+// Pass 1 with the workgroup's nonzeros grouped by destination block first:
+// each loads kTile of them, counts them per block (LDS atomics; the rank an
+// atomic returns only places an element inside its block's LDS segment), and
+// stores them from LDS in block order, so that the lanes of one store write
+// the consecutive slots of a few blocks' runs instead of 64 scattered slots.
+// Every element still goes to dest[p]: the order inside LDS changes which
+// lane stores it, never where.  Needs at most kMaxBlocks blocks.
+constexpr int kMaxBlocks = 4096;
+
+template <typename T>
+constexpr int sort_tile() {
+  return sizeof(T) >= 8 ? 4096 : 8192;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_to_staging_sorted(const T* __restrict__ values,
+                                                           const int32_t* __restrict__ dest, int32_t nnz,
+                                                           int32_t nblocks, T* __restrict__ staging) {
+  constexpr int kTile = sort_tile<T>();
+  constexpr int kPer = kTile / kWG;
+  __shared__ int32_t s_cnt[kMaxBlocks];
+  __shared__ int32_t s_dest[kTile];
+  __shared__ T s_val[kTile];
+  __shared__ int32_t s_wsum[kWG / kWave];
+  const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+  const int64_t base = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * kTile;
+  for (int i = t; i < nblocks; i += kWG) s_cnt[i] = 0;
+  __syncthreads();
+  int32_t d[kPer], rank[kPer];
+  T v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t p = base + u * kWG + t;
+    const bool ok = p < nnz;
+    d[u] = ok ? ld_stream(dest + p) : -1;
+    v[u] = ok ? ld_stream(values + p) : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    rank[u] = -1;
+    if (d[u] >= 0 && d[u] < nnz) rank[u] = atomicAdd(&s_cnt[d[u] / SPX_CSC_BLOCK], 1);
+  }
+  __syncthreads();
+  // exclusive prefix of the block counts (thread t owns blocks [t * per, (t + 1) * per))
+  const int per = (nblocks + kWG - 1) / kWG;
+  int32_t mine = 0;
+  for (int i = 0; i < per; ++i) {
+    const int b = t * per + i;
+    if (b < nblocks) mine += s_cnt[b];
+  }
+  int32_t inc = mine;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int32_t u = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += u;
+  }
+  if (lane == kWave - 1) s_wsum[w] = inc;
+  __syncthreads();
+  int32_t run = inc - mine;
+  int32_t placed = 0;  // elements with a valid destination, all placed below
+  for (int i = 0; i < kWG / kWave; ++i) {
+    if (i < w) run += s_wsum[i];
+    placed += s_wsum[i];
+  }
+  for (int i = 0; i < per; ++i) {
+    const int b = t * per + i;
+    if (b < nblocks) {
+      const int32_t c = s_cnt[b];
+      s_cnt[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    if (rank[u] < 0) continue;
+    const int32_t q = s_cnt[d[u] / SPX_CSC_BLOCK] + rank[u];
+    s_dest[q] = d[u];
+    s_val[q] = v[u];
+  }
+  __syncthreads();
+  for (int32_t i = t; i < placed; i += kWG) {
+    const int32_t dd = s_dest[i];
+    if (dd >= 0 && dd < nnz) staging[dd] = s_val[i];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_from_staging(const T* __restrict__ staging,
                                                       const uint16_t* __restrict__ local, int32_t nnz,
@@ -434,8 +521,16 @@ extern "C" spx_status csr_values_to_csc(int32_t nnz, const int32_t* dest, const 
   const unsigned nb = static_cast<unsigned>((static_cast<int64_t>(nnz) + SPX_CSC_BLOCK - 1) / SPX_CSC_BLOCK);
   const int64_t tiles = (static_cast<int64_t>(nnz) + kWG * kStagePerThread - 1) / (kWG * kStagePerThread);
   const unsigned g1 = static_cast<unsigned>((tiles + 7) / 8 * 8);
+  const int32_t nblocks = static_cast<int32_t>(nb);
 #define SPX_TO_CSC(T)                                                                                    \
-  k_to_staging<T><<<g1, kWG, 0, st>>>(static_cast<const T*>(values), dest, nnz, static_cast<T*>(staging)); \
+  if (nblocks <= kMaxBlocks) {                                                                           \
+    const int64_t st_tiles = (static_cast<int64_t>(nnz) + sort_tile<T>() - 1) / sort_tile<T>();         \
+    const unsigned gs = static_cast<unsigned>((st_tiles + 7) / 8 * 8);                                   \
+    k_to_staging_sorted<T><<<gs, kWG, 0, st>>>(static_cast<const T*>(values), dest, nnz, nblocks,       \
+                                                static_cast<T*>(staging));                               \
+  } else {                                                                                               \
+    k_to_staging<T><<<g1, kWG, 0, st>>>(static_cast<const T*>(values), dest, nnz, static_cast<T*>(staging)); \
+  }                                                                                                      \
   SPX_LAUNCHED("k_to_staging");                                                                          \
   k_from_staging<T><<<nb, kWG, 0, st>>>(static_cast<const T*>(staging), local, nnz, static_cast<T*>(values_csc)); \
   SPX_LAUNCHED("k_from_staging");                                                                        \

@@ -166,12 +166,15 @@ def test_spmv_t_parity(spx, torch, kind, k):
     assert np.array_equal(outs[1].view(np.uint64), again.view(np.uint64))  # deterministic
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
-@pytest.mark.parametrize("nnz", [0, 1, 8191, 8192, 3 * 8192 + 77])
+@pytest.mark.parametrize("dtype,nnz", [(d, n) for d in ("f64", "f32", "bf16")
+                                       for n in (0, 1, 8191, 8192, 3 * 8192 + 77, 300_001)]
+                         + [("f32", 4096 * 8192 + 5)])
 def test_values_to_csc_is_the_permutation(spx, torch, dtype, nnz):
     """The two-pass block transposition returns values[perm] bit for bit:
-    empty, one element, one block minus one, exactly one block, and several
-    blocks with a ragged last one (perm: a random permutation)."""
+    empty, one element, one block minus one, exactly one block, several
+    blocks with a ragged last one, and (f32) just past the 4,096 blocks that
+    the workgroup-sorted first pass handles, so the plain pass runs (perm: a
+    random permutation)."""
     from paper_1302_1078_amd.ops import CSCIndex
     rng = np.random.default_rng(nnz)
     perm = rng.permutation(nnz).astype(np.int32)
