@@ -19,9 +19,10 @@ import sys
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c3", "stencil27"])
-    ap.add_argument("--op", default="spmv", choices=["spmv", "spmm", "xgather", "colstream"],
+    ap.add_argument("--op", default="spmv", choices=["spmv", "spmm", "xgather", "colstream", "autograd"],
                     help="xgather / colstream: the index-gather probe over the matrix's colind "
-                         "(with / without the x reads)")
+                         "(with / without the x reads); autograd: forward + backward through the "
+                         "autograd Function (values and x both require gradients)")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--reps", type=int, default=5)
@@ -38,6 +39,7 @@ def main(argv=None):
     import torch
 
     import spgen
+    from . import autograd as ops_autograd
     from . import ops
     from ._lib import PlanOpts
 
@@ -64,6 +66,20 @@ def main(argv=None):
     X = X.reshape(A.n, k) if k > 1 else X
     Y = torch.empty((A.m, k) if k > 1 else (A.m,), dtype=xt, device=dev)
     flush = None if args.no_flush else torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+    if args.op == "autograd":
+        g = ops_autograd.GradContext(A)
+        v = A.values.clone().requires_grad_(True)
+        x = torch.from_numpy(spgen.uniform(A.n, 0)).to(dev).to(xt).requires_grad_(True)
+        dy = torch.from_numpy(spgen.normal(A.m, 1)).to(dev).to(xt)
+        for _ in range(args.reps):
+            if flush is not None:
+                ops.probe("flush", flush)
+            v.grad = x.grad = None
+            ops_autograd.spmv_autograd(v, x, g).backward(dy)
+        torch.cuda.synchronize()
+        print(f"ran autograd forward + backward on {args.workload} ({A.nnz} nnz, {args.dtype}) x{args.reps}",
+              flush=True)
+        return
     if args.op in ("xgather", "colstream"):
         x = torch.from_numpy(spgen.uniform(A.n, 0)).to(dev)
         for _ in range(args.reps):
