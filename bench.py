@@ -643,6 +643,14 @@ def main():
     gather["spmv_x_elems_g_per_s"] = nnz / float(tv.mean()) / 1e9
     detail["gather_ceiling"] = gather
     detail["latency"] = chase_latency(torch, spx, dev)
+    # the paper's own best figures: another machine and other (UFL) matrices, so context only
+    detail["paper_context"] = {
+        "hardware": "Intel Xeon Phi SE10P (Knights Corner, 61 cores at 1.05 GHz)",
+        "precision": "FP64 CRS, int32 indices",
+        "spmv_gflops_best": 22.0,        # Sec. 4: best of 22 matrices, compiler-vectorised
+        "spmv_gflops_bandwidth_cap": 30.0,  # Sec. 4.2: 180 GB/s sustained x 1/6 flop per byte
+        "spmm_k16_gflops_best": 128.0,   # Sec. 5: hand-vectorised, non-temporal Y stores
+        "note": "not comparable workloads; vs_baseline stays null"}
 
     cpu = None
     if not args.no_cpu:
