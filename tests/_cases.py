@@ -103,3 +103,32 @@ def stream_mm_opts(k: int, upper: int = 32, chunk: int = 256, kahan: int = 256):
     import paper_1302_1078_amd as spx
     return spx.PlanOpts.from_dict({"nbins": 3, "upper": [upper, 256], "lanes": [512, 64, 0],
                                    "split_chunk": chunk, "kahan_len": kahan, "max_k": k})
+
+
+U32 = 2.0 ** -24
+
+
+def quantised(A, vdtype, torch):
+    """(GPU CSR with stored values, FP64 widening of the stored values)."""
+    def dev(torch, a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    if vdtype == "f32":
+        q = spgen.to_f32(A.values)
+        vals = dev(torch, q)
+        wide = q.astype(np.float64)
+    else:
+        bits = spgen.to_bf16_bits(A.values)
+        vals = dev(torch, bits.view(np.int16)).view(torch.bfloat16)
+        wide = spgen.bf16_bits_to_f64(bits)
+    import paper_1302_1078_amd as spx
+    G = spx.CSR(dev(torch, A.rowptr), dev(torch, A.colind), vals, (A.m, A.n))
+    return G, oracle.CSR(A.m, A.n, A.rowptr, A.colind, wide)
+
+
+def check_bound(y, y5, S, L, kahan_len, what):
+    err = np.abs(y.astype(np.float64) - y5)
+    comp = L > kahan_len
+    plain_bound = gamma(L + 8, U32) * S
+    comp_bound = U32 * np.abs(y5) + gamma(L, U32) ** 2 * S + 2.0 ** -45 * S
+    assert (err[~comp] <= plain_bound[~comp]).all(), (what, "plain rows")
+    assert (err[comp] <= comp_bound[comp]).all(), (what, "compensated rows")

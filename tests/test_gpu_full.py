@@ -1,0 +1,184 @@
+"""Full-size parity, in the launch configuration the benchmark times (default
+plans, or the autotuned batch), against the FP64 oracle run on the host over
+every output element.  The oracle's inputs are the generators' triplets
+assembled by the oracle itself; nothing it reads comes from the GPU.
+
+  C1  power-law 1,048,576 rows, 16.8 M nonzeros: CSR assembly bit-exact;
+      FP64 SpMV and SpMM (k = 16).
+  C2  27-point stencil on 128^3, 55.7 M nonzeros: SpMV and SpMM (k = 8) with
+      FP64, FP32 and BF16 values.
+  C3  power-law 524,288 rows, FP32: one autograd forward and backward
+      (y, dx = A^T dy, dvalues).
+  C4  the 256-matrix batch with autotuned plans, replayed from a HIP graph.
+  C0  uniform 10,000 rows: SpMV.
+
+FP64 results: every row within 2(L + 2) 2^-53 sum_p |a_p x_p| and rel2 <=
+1e-12.  FP32 / BF16 results: the per-row error bounds of the precision form
+against the oracle on the quantised inputs (U32 = 2^-24; compensated rows
+above kahan_len)."""
+import numpy as np
+import pytest
+
+import oracle
+import spgen
+from _cases import U32, check_bound, gamma
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def spx():
+    import paper_1302_1078_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def upload(spx, torch, coo):
+    return spx.from_coo(coo.m, coo.n, dev(torch, coo.r), dev(torch, coo.c), dev(torch, coo.v))
+
+
+def check_f64(y, A, X, what):
+    """y (m x k) against the oracle: per-row bound and rel2."""
+    X = X.reshape(A.n, -1)
+    y = y.reshape(A.m, -1)
+    L = A.row_lengths().astype(np.float64)
+    absA = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(A.values))
+    ref = oracle.spmm(A, X) if X.shape[1] > 1 else oracle.spmv(A, X[:, 0])[:, None]
+    S = oracle.spmm(absA, np.abs(X)) if X.shape[1] > 1 else oracle.spmv(absA, np.abs(X[:, 0]))[:, None]
+    err = np.abs(y - ref)
+    assert (err <= 2.0 * (L[:, None] + 2.0) * U64 * S).all(), (what, "per-row bound")
+    for j in range(X.shape[1]):
+        assert oracle.rel2(y[:, j], ref[:, j]) <= 1e-12, (what, j)
+
+
+def test_c1_assembly_spmv_spmm(spx, torch):
+    coo = spgen.workload_c1(0)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = upload(spx, torch, coo)
+    del coo
+    assert np.array_equal(G.rowptr.cpu().numpy(), A.rowptr)
+    assert np.array_equal(G.colind.cpu().numpy(), A.colind)
+    assert np.array_equal(G.values.cpu().numpy(), A.values)
+    x = spgen.uniform(A.n, 1)
+    y = spx.spmv(G, dev(torch, x), plan=spx.Plan.for_matrix(G, spx.default_opts(1))).cpu().numpy()
+    check_f64(y, A, x, "C1 SpMV")
+    k = 16
+    X = spgen.uniform(A.n * k, 2).reshape(A.n, k)
+    Y = spx.spmm(G, dev(torch, X), plan=spx.Plan.for_matrix(G, spx.default_opts(k))).cpu().numpy()
+    check_f64(Y, A, X, "C1 SpMM k=16")
+
+
+def test_c2_stencil_precisions(spx, torch):
+    coo = spgen.workload_c2_stencil(0)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = upload(spx, torch, coo)
+    del coo
+    L = A.row_lengths()
+    for k in (1, 8):
+        X64 = spgen.uniform(A.n * k, 7, spgen.TAG_X).reshape(A.n, k)
+        Xq = spgen.to_f32(X64)
+        for vname in ("f64", "f32", "bf16"):
+            if vname == "f64":
+                Gv, Xd, wide = G, dev(torch, X64), None
+            elif vname == "f32":
+                Gv, Xd = G.with_values(G.values.float()), dev(torch, Xq)
+                wide = spgen.to_f32(A.values).astype(np.float64)
+            else:
+                Gv, Xd = G.with_values(G.values.to(torch.bfloat16)), dev(torch, Xq)
+                wide = spgen.bf16_bits_to_f64(spgen.to_bf16_bits(A.values))
+            opts = spx.default_opts(k, Gv.values.dtype)
+            plan = spx.Plan.for_matrix(Gv, opts)
+            if k == 1:
+                y = spx.spmv(Gv, Xd[:, 0].contiguous(), plan=plan).double().cpu().numpy()[:, None]
+            else:
+                y = spx.spmm(Gv, Xd, plan=plan).double().cpu().numpy()
+            if vname == "f64":
+                check_f64(y, A, X64, f"C2 k={k} f64")
+                continue
+            A5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, wide)
+            absA5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(wide))
+            for j in range(k):
+                xq = Xq[:, j].astype(np.float64)
+                y5 = oracle.spmv(A5, xq)
+                S = oracle.spmv(absA5, np.abs(xq))
+                check_bound(y[:, j], y5, S, L, opts.kahan_len, (f"C2 k={k}", vname, j))
+
+
+def test_c3_autograd_step(spx, torch):
+    coo = spgen.workload_c3(0)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = upload(spx, torch, coo)
+    del coo
+    q = spgen.to_f32(A.values)
+    A32 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, q.astype(np.float64))
+    G32 = G.with_values(G.values.float())
+    x = spgen.to_f32(spgen.uniform(A.n, 3))
+    dy = spgen.to_f32(spgen.normal(A.m, 4, spgen.TAG_DY))
+    g = spx.GradContext(G32)
+    v = G32.values.clone().requires_grad_(True)
+    xt = dev(torch, x).requires_grad_(True)
+    y = spx.spmv_autograd(v, xt, g)
+    y.backward(dev(torch, dy))
+    L = A.row_lengths()
+    absA = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(A32.values))
+    xd, dyd = x.astype(np.float64), dy.astype(np.float64)
+    check_bound(y.detach().double().cpu().numpy(), oracle.spmv(A32, xd), oracle.spmv(absA, np.abs(xd)), L,
+                g.plan.opts.kahan_len, "C3 forward")
+    # dx = A^T dy: column j sums its column's products (CSC traversal, plan of the CSC pattern)
+    Lc = np.bincount(A.colind, minlength=A.n)
+    dx5 = oracle.spmv_t(A32, dyd)
+    Sc = oracle.spmv_t(absA, np.abs(dyd))
+    check_bound(xt.grad.double().cpu().numpy(), dx5, Sc, Lc, g.plan_t.opts.kahan_len, "C3 dx")
+    # dvalues[p] = dy[row] * x[col]: one FP32 product, correctly rounded
+    dv5 = oracle.sddmm(A, dyd, xd)
+    dv = v.grad.double().cpu().numpy()
+    assert (np.abs(dv - dv5) <= U32 * np.abs(dv5)).all()
+
+
+def test_c4_batch(spx, torch):
+    from paper_1302_1078_amd import autotune
+    from paper_1302_1078_amd.batch import Batched
+    specs = spgen.batch_specs(256, seed=0)
+    mats, Xs, refs = [], [], []
+    for i, s in enumerate(specs):
+        coo = spgen.batch_matrix(s, 0, i)
+        A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+        G = upload(spx, torch, coo)
+        X = spgen.to_f32(spgen.uniform(A.n * s.k, 1000 + i, spgen.TAG_X).reshape(A.n, s.k))
+        mats.append(G.with_values(G.values.float()))
+        Xs.append(dev(torch, X[:, 0] if s.k == 1 else X))
+        refs.append((A, X))
+    opts = [autotune.tune(G, X, reps=3)[0] for G, X in zip(mats, Xs)]
+    B = Batched(mats, Xs, opts=opts)
+    g = B.capture()
+    g.replay()
+    torch.cuda.synchronize()
+    for i, ((A, X), Y, o) in enumerate(zip(refs, B.Ys, opts)):
+        A5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, spgen.to_f32(A.values).astype(np.float64))
+        absA5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(A5.values))
+        Yh = Y.double().cpu().numpy().reshape(A.m, -1)
+        L = A.row_lengths()
+        for j in range(X.shape[1]):
+            xq = X[:, j].astype(np.float64)
+            check_bound(Yh[:, j], oracle.spmv(A5, xq), oracle.spmv(absA5, np.abs(xq)), L, o.kahan_len,
+                        ("C4", i, j))
+
+
+def test_c0(spx, torch):
+    coo = spgen.workload_c0(0)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    G = upload(spx, torch, coo)
+    x = spgen.uniform(A.n, 5)
+    y = spx.spmv(G, dev(torch, x), plan=spx.Plan.for_matrix(G)).cpu().numpy()
+    check_f64(y, A, x, "C0 SpMV")
