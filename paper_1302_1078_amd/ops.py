@@ -167,9 +167,11 @@ class Plan:
         return self.handle
 
     def __del__(self):
+        # at interpreter exit the module globals may already be gone
         h = getattr(self, "handle", None)
-        if h is not None and h.value and _lib._lib is not None:
-            _lib._lib.csr_plan_destroy(h)
+        lib = getattr(_lib, "_lib", None) if _lib is not None else None
+        if h is not None and h.value and lib is not None:
+            lib.csr_plan_destroy(h)
             self.handle = None
 
 
