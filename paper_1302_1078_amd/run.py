@@ -18,7 +18,9 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c3", "stencil27"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c3", "stencil27", "c4"],
+                    help="c4: the 256-matrix batch (FP32 values, k in {1, 4, 16}); runs the batch "
+                         "and then the same products launched one by one, --reps times each")
     ap.add_argument("--op", default="spmv", choices=["spmv", "spmm", "xgather", "colstream", "autograd"],
                     help="xgather / colstream: the index-gather probe over the matrix's colind "
                          "(with / without the x reads); autograd: forward + backward through the "
@@ -46,6 +48,9 @@ def main(argv=None):
     dev = torch.device("cuda", 0)
     if args.bandwidth:
         bandwidth(torch, ops, dev)
+        return
+    if args.workload == "c4":
+        batch_vs_single(torch, ops, spgen, dev, args.reps)
         return
     if args.probe_copy_mib:
         a = torch.zeros(args.probe_copy_mib << 17, dtype=torch.float64, device=dev)
@@ -104,6 +109,39 @@ def main(argv=None):
     torch.cuda.synchronize()
     print(f"ran {args.op} on {args.workload} ({A.m} rows, {A.nnz} nnz, k={k}, {args.dtype}) "
           f"x{args.reps} per plan, {len(plans)} plan(s)", flush=True)
+
+
+def batch_vs_single(torch, ops, spgen, dev, reps: int):
+    """The 256-matrix batch (default plans, stream bins kept as tiles, as a
+    batch runs them) and the same products as single launches."""
+    from ._lib import SPX_FLAG_KEEP_STREAM
+    from .batch import Batched
+    mats, Xs, opts = [], [], []
+    for i, s in enumerate(spgen.batch_specs(256, seed=0)):
+        coo = spgen.batch_matrix(s, 0, i)
+        A = ops.from_coo(coo.m, coo.n, torch.from_numpy(coo.r).to(dev), torch.from_numpy(coo.c).to(dev),
+                         torch.from_numpy(coo.v).to(dev))
+        A = A.with_values(A.values.float())
+        X = torch.from_numpy(spgen.uniform(A.n * s.k, 1000 + i, spgen.TAG_X)).to(dev).float()
+        Xs.append(X if s.k == 1 else X.reshape(A.n, s.k))
+        o = ops.default_opts(s.k, torch.float32)
+        o.flags |= SPX_FLAG_KEEP_STREAM
+        mats.append(A)
+        opts.append(o)
+    plans = [ops.Plan.for_matrix(A, o) for A, o in zip(mats, opts)]
+    outs = [torch.empty((A.m,) if X.dim() == 1 else (A.m, X.shape[1]), device=dev) for A, X in zip(mats, Xs)]
+    B = Batched(mats, Xs, opts=opts)
+    for _ in range(reps):
+        B.run()
+        torch.cuda.synchronize()
+        for A, X, p, Y in zip(mats, Xs, plans, outs):
+            if X.dim() == 1:
+                ops.spmv(A, X, y=Y, plan=p)
+            else:
+                ops.spmm(A, X, Y=Y, plan=p)
+        torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(outs, B.Ys))
+    print(f"ran the 256-matrix batch and its single launches x{reps}; bitwise equal: {same}", flush=True)
 
 
 def bandwidth(torch, ops, dev, reps: int = 20):
