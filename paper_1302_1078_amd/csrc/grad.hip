@@ -343,8 +343,9 @@ __global__ __launch_bounds__(kWG) void k_to_staging(const T* __restrict__ values
 }
 
 // Pass 1 with the workgroup's nonzeros grouped by destination block first
-// (tiles of 4,096 FP32 nonzeros: 40 KB of LDS, 4 workgroups per CU; twice
-// the tile halved the occupancy and ran 25 % slower):
+// (tiles of 4,096 FP32 nonzeros, 32 KB of LDS plus the block-count table
+// sized to the matrix; twice the tile halved the occupancy and ran 25 %
+// slower):
 // each loads kTile of them, counts them per block (LDS atomics; the rank an
 // atomic returns only places an element inside its block's LDS segment), and
 // stores them from LDS in block order, so that the lanes of one store write
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(kWG) void k_to_staging_sorted(const T* __restrict__
                                                            int32_t nblocks, T* __restrict__ staging) {
   constexpr int kTile = sort_tile<T>();
   constexpr int kPer = kTile / kWG;
-  __shared__ int32_t s_cnt[kMaxBlocks];
+  extern __shared__ int32_t s_cnt[];  // nblocks entries (dynamic LDS, sized by the launch)
   __shared__ int32_t s_dest[kTile];
   __shared__ T s_val[kTile];
   __shared__ int32_t s_wsum[kWG / kWave];
@@ -528,7 +529,8 @@ extern "C" spx_status csr_values_to_csc(int32_t nnz, const int32_t* dest, const 
   if (nblocks <= kMaxBlocks) {                                                                           \
     const int64_t st_tiles = (static_cast<int64_t>(nnz) + sort_tile<T>() - 1) / sort_tile<T>();         \
     const unsigned gs = static_cast<unsigned>((st_tiles + 7) / 8 * 8);                                   \
-    k_to_staging_sorted<T><<<gs, kWG, 0, st>>>(static_cast<const T*>(values), dest, nnz, nblocks,       \
+    k_to_staging_sorted<T><<<gs, kWG, sizeof(int32_t) * nblocks, st>>>(static_cast<const T*>(values), dest, \
+                                                                     nnz, nblocks,                        \
                                                 static_cast<T*>(staging));                               \
   } else {                                                                                               \
     k_to_staging<T><<<g1, kWG, 0, st>>>(static_cast<const T*>(values), dest, nnz, static_cast<T*>(staging)); \
