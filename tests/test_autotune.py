@@ -1,0 +1,72 @@
+"""Host logic of the autotuner, with the GPU timing replaced by fixed times:
+the default plan (first candidate) is kept unless another is faster by the
+margin; with batch=True candidates are timed with stream bins kept as tiles
+but returned without that flag; decisions are cached under a key that
+carries the tuner's settings."""
+import json
+from types import SimpleNamespace
+
+import pytest
+import torch
+
+
+@pytest.fixture()
+def fake_matrix():
+    rowptr = torch.tensor([0, 2, 3, 5], dtype=torch.int32)
+    colind = torch.tensor([0, 2, 1, 0, 2], dtype=torch.int32)
+    values = torch.ones(5, dtype=torch.float64)
+    return SimpleNamespace(m=3, n=3, nnz=5, rowptr=rowptr, colind=colind, values=values)
+
+
+def run_tune(monkeypatch, A, rel_times, **kw):
+    from paper_1302_1078_amd import autotune
+    seen = []
+
+    def fake_time(A_, X_, opts, reps=5, calls=8):
+        i = len(seen)
+        seen.append(opts)
+        return 1.0 * rel_times[i] if i < len(rel_times) else 1.0
+
+    monkeypatch.setattr(autotune, "time_opts", fake_time)
+    x = torch.ones(3, dtype=torch.float64)
+    best, rep = autotune.tune(A, x, **kw)
+    return best, rep, seen
+
+
+def test_default_kept_unless_clearly_faster(monkeypatch, fake_matrix):
+    from paper_1302_1078_amd import autotune
+    n = len(autotune.candidates(1))
+    best, rep, _ = run_tune(monkeypatch, fake_matrix, [1.0] * n)
+    assert rep["choice"] == 0
+    times = [1.0] * n
+    times[2] = 0.97  # 3 % faster: within the 5 % margin, the default stays
+    assert run_tune(monkeypatch, fake_matrix, times)[1]["choice"] == 0
+    times[2] = 0.90  # 10 % faster: chosen
+    best, rep, _ = run_tune(monkeypatch, fake_matrix, times)
+    assert rep["choice"] == 2
+    assert best.to_dict() == autotune.candidates(1)[2].to_dict()
+    assert run_tune(monkeypatch, fake_matrix, times, margin=0.2)[1]["choice"] == 0
+
+
+def test_batch_timing_keeps_stream_tiles(monkeypatch, fake_matrix):
+    from paper_1302_1078_amd._lib import SPX_FLAG_KEEP_STREAM
+    best, _, seen = run_tune(monkeypatch, fake_matrix, [], batch=True)
+    assert seen and all(o.flags & SPX_FLAG_KEEP_STREAM for o in seen)
+    assert not (best.flags & SPX_FLAG_KEEP_STREAM)
+    _, _, seen = run_tune(monkeypatch, fake_matrix, [], batch=False)
+    assert not any(o.flags & SPX_FLAG_KEEP_STREAM for o in seen)
+
+
+def test_cache_key_carries_settings(monkeypatch, fake_matrix, tmp_path):
+    from paper_1302_1078_amd import autotune
+    cache = str(tmp_path / "tune.json")
+    n = len(autotune.candidates(1))
+    times = [1.0] * n
+    times[1] = 0.5
+    best, rep, _ = run_tune(monkeypatch, fake_matrix, times, cache_path=cache)
+    assert rep["choice"] == 1 and not rep["cached"]
+    _, rep2, seen = run_tune(monkeypatch, fake_matrix, times, cache_path=cache)
+    assert rep2["cached"] and not seen  # reused, nothing timed
+    _, rep3, seen = run_tune(monkeypatch, fake_matrix, times, cache_path=cache, margin=0.01)
+    assert not rep3["cached"] and seen  # other settings: tuned again
+    assert len(json.load(open(cache))) == 2
