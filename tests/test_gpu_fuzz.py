@@ -1,7 +1,8 @@
 """Seeded random configurations against the oracle: plan options (bins,
 thresholds, lane widths, stream and split bins, split chunk, compensation
 threshold, flags), SpMM width, value type and matrix kind are drawn from a
-fixed seed per case, so every run checks the same 60 combinations.  Each
+fixed seed per case, so every run checks the same combinations (60
+products, 24 backward cases, 8 batches).  Each
 product must meet the per-row error bound: FP64 2(L + 2) 2^-53 sum |a x|;
 FP32 / BF16 the precision-form bounds against the quantised inputs."""
 import numpy as np
@@ -80,3 +81,69 @@ def test_random_configuration(spx, torch, case):
             assert (np.abs(y[:, j] - ref) <= 2.0 * (L + 2.0) * 2.0 ** -53 * S).all(), (what, j)
         else:
             check_bound(y[:, j], ref, S, L, opts.kahan_len, (what, j))
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_random_backward(spx, torch, case):
+    """A^T dY by the three transpose paths and the sampled dot, random plans
+    and widths: FP64 within 2(L + 2) 2^-53 sum |a dy| per column (L = column
+    length); the CSC-values path bitwise equal to the path through perm."""
+    from paper_1302_1078_amd.ops import CSCIndex
+    rng = np.random.default_rng(5000 + case)
+    kind = KINDS[int(rng.integers(len(KINDS)))]
+    A = matrix(kind, seed=int(rng.integers(1 << 16)))
+    k = int(rng.choice([1, 1, 2, 3, 8]))
+    G = spx.CSR(*(torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+                  for a in (A.rowptr, A.colind, A.values)), (A.m, A.n))
+    dY = spgen.normal(A.m * k, int(rng.integers(1 << 16))).reshape(A.m, k)
+    X = spgen.uniform(A.n * k, int(rng.integers(1 << 16))).reshape(A.n, k)
+    dYd = torch.from_numpy(dY if k > 1 else dY[:, 0].copy()).to("cuda:0")
+    Xd = torch.from_numpy(X if k > 1 else X[:, 0].copy()).to("cuda:0")
+    idx = spx.transpose_index(G)
+    plan_t = spx.Plan(idx.colptr, A.n, A.m, A.nnz, random_opts(spx, rng, k))
+    plan = spx.Plan.for_matrix(G, random_opts(spx, rng, k))
+    vcsc = spx.values_to_csc(G.values, spx.csc_value_map(idx))
+    d_perm = spx.spmv_t(G, dYd, mode=0, index=idx, plan=plan_t).cpu().numpy().reshape(A.n, k)
+    d_csc = spx.spmv_t(G.with_values(vcsc), dYd, mode=0, index=CSCIndex(idx.colptr, idx.rowind, None),
+                       plan=plan_t).cpu().numpy().reshape(A.n, k)
+    d_atom = spx.spmv_t(G, dYd, mode=1, plan=plan).cpu().numpy().reshape(A.n, k)
+    assert np.array_equal(d_perm.view(np.uint64), d_csc.view(np.uint64)), case
+    Lc = np.bincount(A.colind, minlength=A.n).astype(np.float64)
+    absA = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(A.values))
+    ref = oracle.spmv_t(A, dY)
+    S = oracle.spmv_t(absA, np.abs(dY))
+    for d in (d_perm, d_atom):
+        assert (np.abs(d - ref) <= 2.0 * (Lc[:, None] + 2.0) * 2.0 ** -53 * S).all(), case
+    dv = spx.sddmm(G, dYd, Xd, plan=plan).cpu().numpy()
+    dv_ref = oracle.sddmm(A, dY, X)
+    assert (np.abs(dv - dv_ref) <= (k + 1) * 2.0 ** -53 * oracle.sddmm(A, np.abs(dY), np.abs(X))).all(), case
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_batch(spx, torch, case):
+    """A batch of random matrices, widths and plans: every result bitwise
+    equal to its single launch with stream bins kept as tiles."""
+    from paper_1302_1078_amd._lib import SPX_FLAG_KEEP_STREAM
+    from paper_1302_1078_amd.batch import Batched
+    rng = np.random.default_rng(9000 + case)
+    dt = torch.float32 if rng.random() < 0.5 else torch.float64
+    mats, Xs, opts = [], [], []
+    for i in range(int(rng.integers(1, 12))):
+        A = matrix(KINDS[int(rng.integers(len(KINDS)))], seed=int(rng.integers(1 << 16)))
+        k = int(rng.choice([1, 1, 4, 16]))
+        G = spx.CSR(*(torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+                      for a in (A.rowptr, A.colind, A.values)), (A.m, A.n))
+        X = torch.from_numpy(spgen.uniform(A.n * k, int(rng.integers(1 << 16))).reshape(A.n, k)).to("cuda:0")
+        mats.append(G.with_values(G.values.to(dt)))
+        Xs.append((X[:, 0].contiguous() if k == 1 else X).to(dt))
+        o = random_opts(spx, rng, k)
+        o.flags &= ~2  # the batch serves only the vector X layouts
+        opts.append(o)
+    B = Batched(mats, Xs, opts=opts)
+    Ys = [Y.clone() for Y in B.run()]
+    for G, X, o, Y in zip(mats, Xs, opts, Ys):
+        ko = spx.PlanOpts.from_dict(o.to_dict())
+        ko.flags |= SPX_FLAG_KEEP_STREAM
+        p = spx.Plan.for_matrix(G, ko)
+        want = spx.spmv(G, X, plan=p) if X.dim() == 1 else spx.spmm(G, X, plan=p)
+        assert torch.equal(want, Y), case
