@@ -157,12 +157,15 @@ __device__ __forceinline__ void accumulate(const ProdArgs& a, int32_t p0, int32_
 
 // Begin/end of the rows served by a row group: binned rows read their id from
 // row_perm and their nonzero range from prange (both precomputed by the plan,
-// one independent load each); unbinned rows read rowptr.
+// one independent load each); unbinned rows read rowptr.  Each header is read
+// once per product, so its loads are non-temporal like the matrix stream and
+// leave L2 to the gathered x lines.
 __device__ __forceinline__ void row_range(const ProdArgs& a, const BinDesc& d, int idx, int32_t& row,
                                           int32_t& p0, int32_t& p1) {
   if (a.row_perm) {
-    row = a.row_perm[d.row_begin + idx];
-    const int2 pr = reinterpret_cast<const int2*>(a.prange)[d.row_begin + idx];
+    row = ld_stream(a.row_perm + d.row_begin + idx);
+    using I2 = VecT<int32_t, 2>::type;
+    const I2 pr = ld_stream(reinterpret_cast<const I2*>(a.prange) + d.row_begin + idx);
     p0 = pr.x;
     p1 = pr.y;
   } else {
