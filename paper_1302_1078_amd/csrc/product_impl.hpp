@@ -386,6 +386,7 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   __shared__ int32_t s_p0[kStreamRows];
   __shared__ AT s_prod[kStreamChunk];
   __shared__ int32_t s_wsum[kWG / kWave];
+  __shared__ int32_t s_end;
   if (tile * kStreamRows >= d.nrows) return;
   const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
   const int idx = tile * kStreamRows + t;
@@ -412,8 +413,16 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   s_off[t] = off;
   s_p0[t] = p0;
   if (t == kWG - 1) s_off[kStreamRows] = total;
+  if (idx == min(d.nrows, (tile + 1) * kStreamRows) - 1) s_end = p1;
   total = __builtin_amdgcn_readfirstlane(total);
   __syncthreads();
+  // Rows of a bin are ascending, so the tile's nonzeros are one contiguous
+  // run exactly when its last row ends total elements after its first row
+  // begins (rows between them that are not in the bin are then empty).  In
+  // that case element j sits at the first row's p0 + j and the search below
+  // is skipped.
+  const int32_t P0 = __builtin_amdgcn_readfirstlane(s_p0[0]);
+  const bool contig = __builtin_amdgcn_readfirstlane(s_end) - P0 == total;
 
   const XT* X = static_cast<const XT*>(a.X);
   const bool comp = C::kComp && (L > a.kahan_len);
@@ -428,21 +437,28 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   using VL = ValueLoad<typename C::VT>;
   using Raw = typename VL::Raw;
   auto fetch = [&](int32_t base, int32_t (&cc)[kStreamPer], Raw (&vv)[kStreamPer]) {
-    int32_t jj[kStreamPer], lo[kStreamPer];
+    int32_t jj[kStreamPer], pp[kStreamPer];
 #pragma unroll
-    for (int u = 0; u < kStreamPer; ++u) {
-      jj[u] = min(base + u * kWG + t, total - 1);
-      lo[u] = 0;
+    for (int u = 0; u < kStreamPer; ++u) jj[u] = min(base + u * kWG + t, total - 1);
+    if (contig) {
+#pragma unroll
+      for (int u = 0; u < kStreamPer; ++u) pp[u] = P0 + jj[u];
+    } else {
+      int32_t lo[kStreamPer];
+#pragma unroll
+      for (int u = 0; u < kStreamPer; ++u) lo[u] = 0;
+#pragma unroll
+      for (int step = kStreamRows / 2; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int u = 0; u < kStreamPer; ++u)
+          if (s_off[lo[u] + step] <= jj[u]) lo[u] += step;
+      }
+#pragma unroll
+      for (int u = 0; u < kStreamPer; ++u) pp[u] = s_p0[lo[u]] + (jj[u] - s_off[lo[u]]);
     }
 #pragma unroll
-    for (int step = kStreamRows / 2; step >= 1; step >>= 1) {
-#pragma unroll
-      for (int u = 0; u < kStreamPer; ++u)
-        if (s_off[lo[u] + step] <= jj[u]) lo[u] += step;
-    }
-#pragma unroll
     for (int u = 0; u < kStreamPer; ++u) {
-      const int32_t p = s_p0[lo[u]] + (jj[u] - s_off[lo[u]]);
+      const int32_t p = pp[u];
       cc[u] = ld_mat<C::kNT>(a.colind + p);
       const int32_t q = a.vperm ? ld_mat<C::kNT>(a.vperm + p) : p;
       vv[u] = VL::template raw<C::kNT>(static_cast<const typename C::VT*>(a.values) + q);
