@@ -162,6 +162,44 @@ def test_spmv_exact_inputs_bit_exact(spx, torch, kind):
         assert np.array_equal(y, ref), (kind, name)
 
 
+def gapped_matrix(gap: str, m: int = 3001, n: int = 500):
+    """Rows of length 20 (even rows) separated by rows outside the stream bin:
+    'empty' gaps keep the nonzeros of the length-20 rows one contiguous run,
+    'short' gaps (length 2) break every tile's run, 'mixed' keeps the first
+    half contiguous and breaks the second half in a few places only."""
+    rng = np.random.default_rng(31)
+    L = np.zeros(m, dtype=np.int64)
+    L[0::2] = 20
+    if gap == "short":
+        L[1::2] = 2
+    elif gap == "mixed":
+        odd = np.arange(1, m, 2)
+        L[odd[(odd > m // 2) & (odd % 194 == 1)]] = 2
+    rowptr = np.zeros(m + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(L)
+    colind = np.concatenate([np.sort(rng.choice(n, int(l), replace=False)) for l in L]).astype(np.int32)
+    A = oracle.CSR(m, n, rowptr, colind, np.zeros(len(colind)))
+    return int_valued(A, seed=5)
+
+
+@pytest.mark.parametrize("gap", ["empty", "short", "mixed"])
+@pytest.mark.parametrize("vname", ["f64", "f32"])
+def test_stream_tiles_contiguous_or_not(spx, torch, gap, vname):
+    """A stream tile whose rows form one contiguous run of nonzeros takes an
+    element's position directly; any other tile searches for its row.  Both
+    kinds of tile, and a matrix holding both, give the oracle's exact sums
+    (small-integer inputs, stream bin for rows longer than 2)."""
+    A = gapped_matrix(gap)
+    x = spgen.small_ints(A.n, 4)
+    ref = oracle.spmv(A, x)
+    vt = torch.float64 if vname == "f64" else torch.float32
+    G = to_gpu(A, vt)
+    opts = keep_stream(spx.PlanOpts.from_dict({"nbins": 2, "upper": [2], "lanes": [1, 512], "max_k": 1}))
+    plan = spx.Plan.for_matrix(G, opts)
+    y = spx.spmv(G, dev_vec(torch, x, vt), plan=plan).double().cpu().numpy()
+    assert np.array_equal(y, ref), (gap, vname)
+
+
 def test_spmv_identity_permutation_laplacian(spx, torch):
     n = 5000
     x = spgen.uniform(n, 1)
