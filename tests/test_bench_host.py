@@ -1,0 +1,61 @@
+"""Host logic of bench.py, no GPU needed: the one-GPU rule, the algorithmic
+byte count of a product (the paper's application bandwidth, Sec. 4.2: every
+matrix, vector and row-pointer byte touched once) and the rule that the
+counter-measured traffic is reported only for the kernel sources it was
+taken with."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_app_bytes_hand_count():
+    # 3 x 4 matrix, 5 nonzeros, k = 2, FP64 values and vectors:
+    # values 5 x 8 + colind 5 x 4 + rowptr 4 x 4 + X 4 x 2 x 8 + Y 3 x 2 x 8
+    assert bench.app_bytes(3, 4, 5, k=2) == 40 + 20 + 16 + 64 + 48
+    # BF16 values, FP32 vectors, k = 1
+    assert bench.app_bytes(3, 4, 5, k=1, sv=2, sx=4) == 10 + 20 + 16 + 16 + 12
+    # the headline matrix: 1,048,576 square, 16,776,698 nonzeros
+    m = 1 << 20
+    assert bench.app_bytes(m, m, 16776698) == 12 * 16776698 + 16 * m + 4 * (m + 1)
+
+
+def test_traffic_only_for_matching_sources(monkeypatch, tmp_path):
+    (tmp_path / "profiles").mkdir()
+    with open(tmp_path / "profiles" / "traffic.json", "w") as f:
+        json.dump({"k_product_spmm_c1": {"bytes_per_launch": 1234, "source_hash": "aaaa"}}, f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: "aaaa")
+    assert bench.traffic_for("k_product_spmm_c1") == 1234.0
+    assert bench.traffic_for("k_product_spmv_c1") is None
+    monkeypatch.setattr(bench, "source_hash", lambda: "bbbb")
+    assert bench.traffic_for("k_product_spmm_c1") is None
+    os.remove(tmp_path / "profiles" / "traffic.json")
+    assert bench.traffic_for("k_product_spmm_c1") is None
+
+
+def test_source_hash_covers_the_product_sources(monkeypatch, tmp_path):
+    """Changing any of the product kernel sources changes the hash."""
+    csrc = tmp_path / "paper_1302_1078_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    names = ("product.hip", "product_impl.hpp", "device.hpp", "plan.hip")
+    for n in names:
+        (csrc / n).write_text(n)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.source_hash()
+    for n in names:
+        (csrc / n).write_text(n + " changed")
+        assert bench.source_hash() != h0, n
+        (csrc / n).write_text(n)
+    assert bench.source_hash() == h0
