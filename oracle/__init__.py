@@ -17,12 +17,18 @@ Functions and the passages they follow:
 * ``flops`` / ``app_bytes`` -- 2 tau k flops (Sec. 3) and the application
   byte count (Sec. 4.2 for SpMV, Sec. 5 for SpMM), generalised to element
   sizes and non-square shapes.
+* ``spmv_abs``       -- sum_p |a_p x_{c_p}| per row, the scale of the
+  floating-point error bounds of a row's dot product.
+* ``rel2``           -- ||y_hat - y||_2 / ||y||_2 in FP64, the absolute norm of
+  the difference when ||y|| = 0.
 * ``ucld``           -- useful cacheline density (Sec. 4.1).
 * ``degree_order``   -- columns by descending nonzero count, ties ascending
   (a locality ordering set beside the paper's RCM step, Sec. 4.4).
 
 Parity: each function is pinned in ``tests/test_oracle.py`` against brute
-force, invariants or closed forms; none is "parity unpinned".
+force, invariants or closed forms (``sddmm`` by exact central differences of
+``spmv``/``spmm``, ``rel2`` by hand-computed vectors, ``spmv_abs`` by a dense
+brute force); none is "parity unpinned".
 """
 from __future__ import annotations
 

@@ -273,6 +273,80 @@ def test_adjoint_identity():
     assert abs(lhs - rhs) <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("k", [1, 3])
+def test_sddmm_is_the_central_difference_of_spmv(k):
+    """Independent pin of the sampled dot: f(values) = <dY, A(values) X> is
+    linear in the values, so the central difference (f(v + e_p) - f(v - e_p)) / 2
+    with h = 1 has no truncation error, and with small-integer values, X and
+    dY every sum is exact.  f is evaluated through the oracle's SpMM / SpMV
+    only, so a wrong row or column index, a transposed operand or a dropped
+    term in sddmm shows up as an exact mismatch."""
+    rng = np.random.default_rng(40 + k)
+    m, n = 37, 29
+    r, c, v = rand_coo(rng, m, n, 160, dup=False)
+    A = oracle.csr_from_coo(m, n, r, c, v)
+    X = rng.integers(-8, 9, (n, k)).astype(np.float64)
+    dY = rng.integers(-8, 9, (m, k)).astype(np.float64)
+
+    def f(vals):
+        Av = oracle.CSR(A.m, A.n, A.rowptr, A.colind, vals)
+        Y = oracle.spmm(Av, X) if k > 1 else oracle.spmv(Av, X[:, 0].copy())[:, None]
+        return float((dY * Y).sum())
+
+    fd = np.empty(A.nnz)
+    for p in range(A.nnz):
+        e = np.zeros(A.nnz)
+        e[p] = 1.0
+        fd[p] = (f(A.values + e) - f(A.values - e)) / 2.0
+    got = oracle.sddmm(A, dY[:, 0].copy(), X[:, 0].copy()) if k == 1 else oracle.sddmm(A, dY, X)
+    assert (got == fd).all()
+
+
+def test_rel2_hand_computed():
+    """rel2 = ||y_hat - y_ref||_2 / ||y_ref||_2 on hand-computed vectors: a
+    swapped argument order, a max-norm or a 1-norm each give another number."""
+    # ||[3, 4]|| = 5 and the difference [0, 1] has norm 1
+    assert oracle.rel2([3.0, 5.0], [3.0, 4.0]) == 0.2
+    # swapped: 1 / ||[3, 5]|| = 1 / sqrt(34)
+    assert oracle.rel2([3.0, 4.0], [3.0, 5.0]) == 1.0 / np.sqrt(34.0)
+    # difference [1, 1]: 2-norm sqrt(2) (max-norm would give 1, 1-norm 2)
+    assert oracle.rel2([4.0, 5.0], [3.0, 4.0]) == np.sqrt(2.0) / 5.0
+    # [1, 2, 2] has norm 3; difference [2, -1, 2] has norm 3
+    assert oracle.rel2([3.0, 1.0, 4.0], [1.0, 2.0, 2.0]) == 1.0
+    # matrices are measured as one flattened vector (Frobenius norm)
+    assert oracle.rel2([[3.0], [5.0]], [[3.0], [4.0]]) == 0.2
+    # a vanishing reference falls back to the absolute norm of the difference
+    assert oracle.rel2([3.0, 4.0], [0.0, 0.0]) == 5.0
+    assert oracle.rel2([0.0, 0.0], [0.0, 0.0]) == 0.0
+    # equal inputs
+    assert oracle.rel2([1e-300, -7.0], [1e-300, -7.0]) == 0.0
+
+
+def test_spmv_abs_brute_force():
+    """spmv_abs(A, x)_i = sum_p |a_p x_{c_p}| = (|A| |x|)_i, checked exactly on
+    integers against a dense brute force; x has mixed signs so that taking
+    the absolute value after the sum (|A x|) would fail."""
+    rng = np.random.default_rng(51)
+    m, n = 45, 38
+    r, c, v = rand_coo(rng, m, n, 300)
+    A = oracle.csr_from_coo(m, n, r, c, v)
+    x = rng.integers(-8, 9, n).astype(np.float64)
+    Di = np.abs(dense(A)).astype(np.int64)
+    S = oracle.spmv_abs(A, x)
+    assert (S == (Di @ np.abs(x).astype(np.int64))).all()
+    assert (S > np.abs(oracle.spmv(A, x))).any()
+    # an empty row gives +0.0
+    B = oracle.csr_from_coo(3, 4, [0, 2], [1, 3], [2.0, -5.0])
+    assert list(oracle.spmv_abs(B, np.array([1.0, -3.0, 7.0, 2.0]))) == [6.0, 0.0, 10.0]
+    # floats: within rounding of the dense |A| |x|, and never below |A x|
+    rf, cf, vf = rand_coo(rng, m, n, 300, ints=False)
+    F = oracle.csr_from_coo(m, n, rf, cf, vf)
+    xf = rng.uniform(-1, 1, n)
+    Sf = oracle.spmv_abs(F, xf)
+    assert np.allclose(Sf, np.abs(dense(F)) @ np.abs(xf), rtol=1e-14, atol=0)
+    assert (Sf >= np.abs(oracle.spmv(F, xf)) * (1 - 1e-15)).all()
+
+
 def test_sddmm_closed_form():
     coo = spgen.powerlaw(800, 900, 2.0, 200, 10.0, seed=7)
     A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
