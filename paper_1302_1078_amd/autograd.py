@@ -19,35 +19,61 @@ from .ops import (CSCIndex, CSR, Plan, csc_value_map, default_opts, sddmm, spmm,
 
 
 class GradContext:
-    """Per-pattern state reused across calls: forward plan, CSC index and the
-    plan of the CSC pattern (for the deterministic transpose)."""
+    """Per-pattern state reused across calls: forward plans, CSC index and the
+    plans of the CSC pattern (for the deterministic transpose).  Plans are
+    kept per number of right-hand sides k (a plan with split rows serves
+    products up to its max_k), so a 2-D X of any width gets a plan built for
+    it on first use; `k` only picks the plans built up front."""
 
     def __init__(self, A: CSR, mode: int = 0, plans: bool = True, k: int = 1, csc_values: bool = True):
         self.A = A
         self.mode = mode
-        self.plan = Plan.for_matrix(A, default_opts(k, A.values.dtype)) if plans else None
+        self.plans = plans
+        self._fwd = {}
+        self._csc = {}
         self.index = transpose_index(A) if mode == 0 else None
-        self.plan_t = None
-        if plans and mode == 0:
-            self.plan_t = Plan(self.index.colptr, A.n, A.m, A.nnz, default_opts(k, A.values.dtype))
         self.vmap = csc_value_map(self.index) if (mode == 0 and csc_values) else None
         self.index_v = CSCIndex(self.index.colptr, self.index.rowind, None) if self.vmap is not None else None
+        self.plan = self.plan_for(k)
+        self.plan_t = self.plan_t_for(k)
+
+    def plan_for(self, k: int):
+        """Plan of the CSR pattern for products with k right-hand sides."""
+        if not self.plans:
+            return None
+        if k not in self._fwd:
+            self._fwd[k] = Plan.for_matrix(self.A, default_opts(k, self.A.values.dtype))
+        return self._fwd[k]
+
+    def plan_t_for(self, k: int):
+        """Plan of the CSC pattern (n rows) for the mode-0 transpose with k columns."""
+        if not self.plans or self.mode != 0:
+            return None
+        if k not in self._csc:
+            A = self.A
+            self._csc[k] = Plan(self.index.colptr, A.n, A.m, A.nnz, default_opts(k, A.values.dtype))
+        return self._csc[k]
 
     def transpose(self, A: CSR, dy: torch.Tensor) -> torch.Tensor:
         """A^T dy by this context's mode."""
+        k = 1 if dy.dim() == 1 else dy.shape[1]
         if self.mode != 0:
             return spmv_t(A, dy, mode=1, plan=self.plan)
+        plan_t = self.plan_t_for(k)
         if self.vmap is None:
-            return spmv_t(A, dy, mode=0, index=self.index, plan=self.plan_t)
+            return spmv_t(A, dy, mode=0, index=self.index, plan=plan_t)
         vcsc = values_to_csc(A.values, self.vmap)
-        return spmv_t(A.with_values(vcsc), dy, mode=0, index=self.index_v, plan=self.plan_t)
+        return spmv_t(A.with_values(vcsc), dy, mode=0, index=self.index_v, plan=plan_t)
 
 
 class SpMVFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, values: torch.Tensor, x: torch.Tensor, gctx: GradContext):
         A = gctx.A.with_values(values)
-        y = spmv(A, x, plan=gctx.plan) if x.dim() == 1 else spmm(A, x, plan=gctx.plan)
+        if x.dim() == 1:
+            y = spmv(A, x, plan=gctx.plan_for(1))
+        else:
+            y = spmm(A, x, plan=gctx.plan_for(x.shape[1]))
         ctx.save_for_backward(values, x)
         ctx.gctx = gctx
         return y

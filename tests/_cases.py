@@ -132,3 +132,24 @@ def check_bound(y, y5, S, L, kahan_len, what):
     comp_bound = U32 * np.abs(y5) + gamma(L, U32) ** 2 * S + 2.0 ** -45 * S
     assert (err[~comp] <= plain_bound[~comp]).all(), (what, "plain rows")
     assert (err[comp] <= comp_bound[comp]).all(), (what, "compensated rows")
+
+
+def c3_submatrix(rows: int = 2000, longest: int = 10, seed: int = 0) -> oracle.CSR:
+    """The gradient-check submatrix of the differentiation workload (the
+    524,288 x 524,288 power-law matrix, Zipf(2.0) rows of mean 20): its
+    `longest` longest rows plus rows - longest rows drawn with a seeded
+    generator, in ascending row order, and the columns compacted to the ones
+    those rows touch (values as generated, FP64)."""
+    coo = spgen.workload_c3(0)
+    B = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    del coo
+    L = B.row_lengths()
+    top = np.argsort(-L, kind="stable")[:longest]
+    rest = np.setdiff1d(np.arange(B.m), top)
+    pick = np.sort(np.concatenate([top, np.random.default_rng(seed).choice(rest, rows - longest,
+                                                                            replace=False)]))
+    row_of = B.row_of()
+    keep = np.isin(row_of, pick)
+    r = np.searchsorted(pick, row_of[keep]).astype(np.int32)
+    cols, c = np.unique(B.colind[keep], return_inverse=True)
+    return oracle.csr_from_coo(pick.size, cols.size, r, c.astype(np.int32), B.values[keep])

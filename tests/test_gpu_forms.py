@@ -14,14 +14,14 @@ Differentiation: transpose products, sampled dot and the autograd Function.
 """
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle
 import spgen
-from _cases import (U32, check_bound, gamma, int_valued, keep_stream, matrix, quantised, single_bin_opts,
-                    stream_mm_opts, to_gpu, two_bin_opts)
+from _cases import (U32, c3_submatrix, check_bound, gamma, int_valued, keep_stream, matrix, quantised,
+                    single_bin_opts, stream_mm_opts, to_gpu, two_bin_opts)
 
 pytestmark = pytest.mark.gpu
-
 
 
 @pytest.fixture(scope="module")
@@ -239,19 +239,10 @@ def test_autograd_gradcheck_f64(spx, torch):
                                         eps=1e-6, atol=1e-9, rtol=1e-7)
 
 
-def test_autograd_dense_reference_and_fd_f32(spx, torch):
-    # 2,000-row submatrix of a Zipf(2.0) mean-20 matrix: the 10 longest rows
-    # plus 1,990 seeded rows, columns compacted to the ones touched.
-    coo = spgen.powerlaw(1 << 15, 1 << 15, 2.0, 20_000, 20.0, seed=0)
-    B = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
-    L = B.row_lengths()
-    longest = np.argsort(-L, kind="stable")[:10]
-    rest = np.setdiff1d(np.arange(B.m), longest)
-    rows = np.sort(np.concatenate([longest, np.random.default_rng(0).choice(rest, 1990, replace=False)]))
-    keep = np.isin(B.row_of(), rows)
-    r = np.searchsorted(rows, B.row_of()[keep])
-    cols, c = np.unique(B.colind[keep], return_inverse=True)
-    A = oracle.csr_from_coo(rows.size, cols.size, r, c, B.values[keep])
+def test_autograd_c3_submatrix_reference_and_fd_f32(spx, torch):
+    # the 2,000-row submatrix of the differentiation workload: its 10 longest
+    # rows (18k-19k nonzeros, split rows) plus 1,990 seeded rows
+    A = c3_submatrix()
     A32 = spx.CSR(dev(torch, A.rowptr), dev(torch, A.colind), dev(torch, spgen.to_f32(A.values)), (A.m, A.n))
     x = spgen.to_f32(spgen.uniform(A.n, 7))
     dy = spgen.to_f32(spgen.normal(A.m, 8))
@@ -260,17 +251,21 @@ def test_autograd_dense_reference_and_fd_f32(spx, torch):
     xt = dev(torch, x).requires_grad_(True)
     y = spx.spmv_autograd(v, xt, g)
     y.backward(dev(torch, dy))
-    # dense reference gradient (FP64 on the host)
-    D = np.zeros((A.m, A.n))
-    D[A.row_of(), A.colind] = spgen.to_f32(A.values)
-    assert np.allclose(xt.grad.cpu().numpy(), D.T @ dy, rtol=1e-5, atol=1e-5)
+    # reference gradients in FP64 on the host: scipy's sparse transpose product
+    # and the closed form of the sampled dot
+    S = sp.csr_matrix((spgen.to_f32(A.values).astype(np.float64), A.colind, A.rowptr), shape=(A.m, A.n))
+    assert np.allclose(xt.grad.cpu().numpy(), S.T @ dy.astype(np.float64), rtol=1e-5, atol=1e-5)
     dv_ref = dy.astype(np.float64)[A.row_of()] * x.astype(np.float64)[A.colind]
     assert np.allclose(v.grad.cpu().numpy(), dv_ref, rtol=1e-6, atol=1e-7)
     # central differences with h = 1: y is bilinear, so there is no truncation error
     f = lambda vv, xx: float(torch.dot(spx.spmv_autograd(vv, xx, g).double(), dev(torch, dy).double()))  # noqa: E731
     rng = np.random.default_rng(1)
+    L = A.row_lengths()
+    long_rows = np.flatnonzero(L > 2048)
+    picks = list(rng.choice(A.nnz, 20, replace=False)) + [int(A.rowptr[A.m] - 1)]
+    picks += [int(A.rowptr[i]) + int(rng.integers(L[i])) for i in long_rows[:5]]  # nonzeros of split rows
     with torch.no_grad():
-        for p in list(rng.choice(A.nnz, 20, replace=False)) + [int(A.rowptr[A.m] - 1)]:
+        for p in picks:
             e = torch.zeros_like(v)
             e[p] = 1.0
             fd = (f(v + e, xt) - f(v - e, xt)) / 2.0
@@ -280,3 +275,21 @@ def test_autograd_dense_reference_and_fd_f32(spx, torch):
             e[j] = 1.0
             fd = (f(v, xt + e) - f(v, xt - e)) / 2.0
             assert abs(fd - float(xt.grad[j])) <= 1e-4 * (1 + abs(fd))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_autograd_c3_submatrix_gradcheck_f64(spx, torch, mode):
+    """torch.autograd.gradcheck (fast mode) in FP64 on the differentiation
+    workload's 2,000-row submatrix, for x and for a 3-column X through a
+    context built for k = 1 (its plans for k = 3 are made on first use).  y is
+    bilinear in (values, x), so the difference step can be 1: the numerical
+    Jacobian then carries rounding error only."""
+    A = c3_submatrix()
+    G = to_gpu(A)
+    g = spx.GradContext(G, mode=mode)
+    v = G.values.clone().requires_grad_(True)
+    x = dev(torch, spgen.uniform(A.n, 4)).requires_grad_(True)
+    X = dev(torch, spgen.uniform(A.n * 3, 5).reshape(A.n, 3)).requires_grad_(True)
+    for inp in (x, X):
+        assert torch.autograd.gradcheck(lambda vv, xx: spx.spmv_autograd(vv, xx, g), (v, inp),
+                                        eps=1.0, atol=1e-8, rtol=1e-8, fast_mode=True)

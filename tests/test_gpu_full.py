@@ -5,8 +5,9 @@ assembled by the oracle itself; nothing it reads comes from the GPU.
 
   C1  power-law 1,048,576 rows, 16.8 M nonzeros: CSR assembly bit-exact;
       FP64 SpMV and SpMM (k = 16).
-  C2  27-point stencil on 128^3, 55.7 M nonzeros: SpMV and SpMM (k = 8) with
-      FP64, FP32 and BF16 values.
+  C2  27-point stencil on 128^3 (55.7 M nonzeros) and the C1 power-law
+      matrix: SpMV (k = 1) and SpMM (k = 8, 32) with FP64, FP32 and BF16
+      values, every element against the oracle.
   C3  power-law 524,288 rows, FP32: one autograd forward and backward
       (y, dx = A^T dy, dvalues).
   C4  the 256-matrix batch with autotuned plans, replayed from a HIP graph.
@@ -15,7 +16,8 @@ assembled by the oracle itself; nothing it reads comes from the GPU.
 FP64 results: every row within 2(L + 2) 2^-53 sum_p |a_p x_p| and rel2 <=
 1e-12.  FP32 / BF16 results: the per-row error bounds of the precision form
 against the oracle on the quantised inputs (U32 = 2^-24; compensated rows
-above kahan_len)."""
+above kahan_len), and their total error against the FP64 oracle on the
+original data."""
 import numpy as np
 import pytest
 
@@ -62,11 +64,22 @@ def check_f64(y, A, X, what):
         assert oracle.rel2(y[:, j], ref[:, j]) <= 1e-12, (what, j)
 
 
-def test_c1_assembly_spmv_spmm(spx, torch):
+@pytest.fixture(scope="module")
+def c2_stencil(spx, torch):
+    coo = spgen.workload_c2_stencil(0)
+    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
+    return A, upload(spx, torch, coo)
+
+
+@pytest.fixture(scope="module")
+def c1_matrix(spx, torch):
     coo = spgen.workload_c1(0)
     A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
-    G = upload(spx, torch, coo)
-    del coo
+    return A, upload(spx, torch, coo)
+
+
+def test_c1_assembly_spmv_spmm(spx, torch, c1_matrix):
+    A, G = c1_matrix  # G assembled on the device from the generator's triplets
     assert np.array_equal(G.rowptr.cpu().numpy(), A.rowptr)
     assert np.array_equal(G.colind.cpu().numpy(), A.colind)
     assert np.array_equal(G.values.cpu().numpy(), A.values)
@@ -79,40 +92,73 @@ def test_c1_assembly_spmv_spmm(spx, torch):
     check_f64(Y, A, X, "C1 SpMM k=16")
 
 
-def test_c2_stencil_precisions(spx, torch):
-    coo = spgen.workload_c2_stencil(0)
-    A = oracle.csr_from_coo(coo.m, coo.n, coo.r, coo.c, coo.v)
-    G = upload(spx, torch, coo)
-    del coo
+def oracle_product(A, X):
+    """FP64 oracle product for X of shape n x k (k = 1 uses the SpMV)."""
+    return oracle.spmm(A, X) if X.shape[1] > 1 else oracle.spmv(A, X[:, 0].copy())[:, None]
+
+
+# unit roundoff of the stored values: BF16 is the round-to-nearest-even of the
+# FP32-rounded value, so it carries both roundings
+U_VALUE = {"f32": U32, "bf16": 2.0 ** -8 + U32 + 2.0 ** -8 * U32}
+
+
+def check_precision_form(spx, torch, A, G, k, what):
+    """The precision form in the benchmark's launch configuration (default
+    plan of each value type) against the oracle, every output element:
+      f64          per-row bound and rel2 <= 1e-12 against the FP64 oracle;
+      f32 / bf16   per-row accumulation bound against the oracle on the
+                   quantised inputs widened exactly (plain rows gamma_{L+8},
+                   compensated rows above kahan_len near one rounding), and
+                   the total error against the FP64 oracle on the original
+                   data: (u_v + u_x + u_v u_x) S + gamma_{L+8} (1 + u_v)(1 + u_x) S,
+                   S = sum_p |a_p x_p|."""
     L = A.row_lengths()
-    for k in (1, 8):
-        X64 = spgen.uniform(A.n * k, 7, spgen.TAG_X).reshape(A.n, k)
-        Xq = spgen.to_f32(X64)
-        for vname in ("f64", "f32", "bf16"):
-            if vname == "f64":
-                Gv, Xd, wide = G, dev(torch, X64), None
-            elif vname == "f32":
-                Gv, Xd = G.with_values(G.values.float()), dev(torch, Xq)
-                wide = spgen.to_f32(A.values).astype(np.float64)
-            else:
-                Gv, Xd = G.with_values(G.values.to(torch.bfloat16)), dev(torch, Xq)
-                wide = spgen.bf16_bits_to_f64(spgen.to_bf16_bits(A.values))
-            opts = spx.default_opts(k, Gv.values.dtype)
-            plan = spx.Plan.for_matrix(Gv, opts)
-            if k == 1:
-                y = spx.spmv(Gv, Xd[:, 0].contiguous(), plan=plan).double().cpu().numpy()[:, None]
-            else:
-                y = spx.spmm(Gv, Xd, plan=plan).double().cpu().numpy()
-            if vname == "f64":
-                check_f64(y, A, X64, f"C2 k={k} f64")
-                continue
-            A5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, wide)
-            absA5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(wide))
-            for j in range(k):
-                xq = Xq[:, j].astype(np.float64)
-                y5 = oracle.spmv(A5, xq)
-                S = oracle.spmv(absA5, np.abs(xq))
-                check_bound(y[:, j], y5, S, L, opts.kahan_len, (f"C2 k={k}", vname, j))
+    X64 = spgen.uniform(A.n * k, 7, spgen.TAG_X).reshape(A.n, k)
+    Xq = spgen.to_f32(X64)
+    absA = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(A.values))
+    ref64 = oracle_product(A, X64)
+    S64 = oracle_product(absA, np.abs(X64))
+    for vname in ("f64", "f32", "bf16"):
+        if vname == "f64":
+            Gv, Xd, wide = G, dev(torch, X64), None
+        elif vname == "f32":
+            Gv, Xd = G.with_values(G.values.float()), dev(torch, Xq)
+            wide = spgen.to_f32(A.values).astype(np.float64)
+        else:
+            Gv, Xd = G.with_values(G.values.to(torch.bfloat16)), dev(torch, Xq)
+            wide = spgen.bf16_bits_to_f64(spgen.to_bf16_bits(A.values))
+        opts = spx.default_opts(k, Gv.values.dtype)
+        plan = spx.Plan.for_matrix(Gv, opts)
+        if k == 1:
+            y = spx.spmv(Gv, Xd[:, 0].contiguous(), plan=plan).double().cpu().numpy()[:, None]
+        else:
+            y = spx.spmm(Gv, Xd, plan=plan).double().cpu().numpy()
+        del Xd, plan
+        if vname == "f64":
+            check_f64(y, A, X64, f"{what} k={k} f64")
+            continue
+        A5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, wide)
+        absA5 = oracle.CSR(A.m, A.n, A.rowptr, A.colind, np.abs(wide))
+        Xq64 = Xq.astype(np.float64)
+        y5 = oracle_product(A5, Xq64)
+        S5 = oracle_product(absA5, np.abs(Xq64))
+        uv = U_VALUE[vname]
+        tot = (uv + U32 + uv * U32) + gamma(L + 8, U32)[:, None] * (1 + uv) * (1 + U32)
+        assert (np.abs(y - ref64) <= tot * S64).all(), (what, k, vname, "total error vs FP64 oracle")
+        for j in range(k):
+            check_bound(y[:, j], y5[:, j], S5[:, j], L, opts.kahan_len, (what, k, vname, j))
+
+
+@pytest.mark.parametrize("k", [1, 8, 32])
+def test_c2_stencil_precisions(spx, torch, c2_stencil, k):
+    A, G = c2_stencil
+    check_precision_form(spx, torch, A, G, k, "C2 27-point 128^3")
+
+
+@pytest.mark.parametrize("k", [1, 8, 32])
+def test_c2_powerlaw_precisions(spx, torch, c1_matrix, k):
+    A, G = c1_matrix
+    check_precision_form(spx, torch, A, G, k, "C2 power-law 1M")
 
 
 def test_c3_autograd_step(spx, torch):
