@@ -135,6 +135,27 @@ spx_status csr_validate(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr
                         const int32_t *colind, int32_t check_sorted, int32_t *status_out,
                         void *stream);
 
+/* The same assembly on HOST arrays (Sec. 3's CRS arrays built from triplets
+ * held in host memory); synchronous, makes no HIP call.  host_r, host_c:
+ * int32[nnz_in]; host_v: f64[nnz_in].  Outputs host_rowptr int32[m+1],
+ * host_colind int32[nnz_in] and host_values f64[nnz_in] (capacity nnz_in,
+ * caller-owned); *host_nnz_out receives the stored count.  Canonical result:
+ * rows ascending, columns strictly ascending in a row, duplicate (i, j)
+ * summed in input order in FP64 -- bitwise the result of csr_from_coo on the
+ * same triplets.  A triplet outside m x n returns SPX_ERR_INVALID with
+ * *host_nnz_out = -1 and the outputs unspecified. */
+spx_status csr_from_coo_host(int32_t m, int32_t n, int64_t nnz_in, const int32_t *host_r,
+                             const int32_t *host_c, const double *host_v, int32_t *host_rowptr,
+                             int32_t *host_colind, double *host_values, int32_t *host_nnz_out);
+
+/* Structural check of CSR arrays in host memory (synchronous, no HIP call):
+ * SPX_OK if rowptr[0] = 0, rowptr is non-decreasing, every entry lies in
+ * [0, nnz], rowptr[m] = nnz and 0 <= colind[p] < n; otherwise
+ * SPX_ERR_INVALID, with spx_last_error() naming the first violation found
+ * (rows before columns).  Column order inside a row is not required. */
+spx_status csr_validate_host(int32_t m, int32_t n, int32_t nnz, const int32_t *host_rowptr,
+                             const int32_t *host_colind);
+
 /* ---------------------------------------------------------------- plans
  * A plan bins the rows of one sparsity pattern by length (row_perm lists bin
  * 0's rows, then bin 1's, ..., ascending inside each bin) and, for a split

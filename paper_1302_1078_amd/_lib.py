@@ -84,6 +84,8 @@ SIGNATURES = {
     "csr_from_coo_workspace_bytes": (ctypes.c_int, [i32, i32, i64, SZ]),
     "csr_from_coo": (ctypes.c_int, [i32, i32, i64, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]),
     "csr_validate": (ctypes.c_int, [i32, i32, i32, P, P, i32, P, P]),
+    "csr_from_coo_host": (ctypes.c_int, [i32, i32, i64, P, P, P, P, P, P, P]),
+    "csr_validate_host": (ctypes.c_int, [i32, i32, i32, P, P]),
     "csr_plan_workspace_bytes": (ctypes.c_int, [i32, i32, ctypes.POINTER(PlanOpts), SZ]),
     "csr_plan_create": (ctypes.c_int, [i32, i32, i32, P, ctypes.POINTER(PlanOpts), P,
                                        ctypes.c_size_t, P, PP]),

@@ -116,6 +116,40 @@ def from_coo(m: int, n: int, r: torch.Tensor, c: torch.Tensor, v: torch.Tensor) 
     return CSR(rowptr, colind[:t], values[:t], (m, n))
 
 
+def from_coo_host(m: int, n: int, r, c, v):
+    """Canonical CSR from host triplets (numpy int32 r, c and float64 v), on
+    the host through csr_from_coo_host; returns numpy (rowptr, colind, values)."""
+    import numpy as np
+    L = _lib.load()
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    if not (r.shape == c.shape == v.shape) or r.ndim != 1:
+        raise ValueError("r, c and v must be 1-D arrays of one length")
+    nnz_in = int(r.size)
+    rowptr = np.empty(m + 1, dtype=np.int32)
+    colind = np.empty(max(nnz_in, 1), dtype=np.int32)
+    values = np.empty(max(nnz_in, 1), dtype=np.float64)
+    nnz_out = ctypes.c_int32()
+    check(L.csr_from_coo_host(m, n, nnz_in, r.ctypes.data, c.ctypes.data, v.ctypes.data, rowptr.ctypes.data,
+                              colind.ctypes.data, values.ctypes.data, ctypes.byref(nnz_out)),
+          "csr_from_coo_host")
+    t = nnz_out.value
+    return rowptr, colind[:t].copy(), values[:t].copy()
+
+
+def validate_host(m: int, n: int, rowptr, colind) -> None:
+    """Raise SpxError unless the host CSR arrays are structurally valid."""
+    import numpy as np
+    L = _lib.load()
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    colind = np.ascontiguousarray(colind, dtype=np.int32)
+    if rowptr.size != m + 1:
+        raise ValueError("rowptr must have m + 1 entries")
+    check(L.csr_validate_host(m, n, int(colind.size), rowptr.ctypes.data, colind.ctypes.data),
+          "csr_validate_host")
+
+
 def validate(A: CSR, check_sorted: bool = True) -> int:
     L = _lib.load()
     status = torch.empty(1, dtype=torch.int32, device=A.device)

@@ -147,3 +147,94 @@ def test_size_limits_checked_before_any_work(lib):
     assert b"split_chunk" in lib.spx_last_error()
     o.split_chunk = 2**24
     assert lib.csr_plan_workspace_bytes(10, 100, ctypes.byref(o), ctypes.byref(sz)) == 0
+
+
+# ---------------------------------------------------------------- host assembly and validation
+
+def test_from_coo_host_bit_exact_against_oracle(lib):
+    """csr_from_coo_host (the library's host assembly, a two-pass counting
+    sort) gives the oracle's CSR bit for bit: duplicates summed in input
+    order, empty rows, shuffled input, m != n."""
+    import numpy as np
+    import oracle
+    import paper_1302_1078_amd as spx
+    import spgen
+    rng = np.random.default_rng(3)
+    cases = []
+    base = spgen.powerlaw(3000, 2500, 2.0, 800, 12.0, seed=2)
+    dup = rng.choice(base.r.size, base.r.size // 10, replace=False)
+    r = np.concatenate([base.r, base.r[dup]])
+    c = np.concatenate([base.c, base.c[dup]])
+    v = np.concatenate([base.v, rng.uniform(-1, 1, dup.size)])
+    p = rng.permutation(r.size)
+    cases.append((base.m, base.n, r[p], c[p], v[p]))
+    # 1e16 + 1 - 1e16: only the input order gives 0
+    cases.append((2, 4, np.array([1, 1, 1, 0]), np.array([3, 3, 3, 0]), np.array([1e16, 1.0, -1e16, 2.0])))
+    cases.append((5, 0, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0)))
+    cases.append((0, 5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0)))
+    for m, n, r, c, v in cases:
+        A = oracle.csr_from_coo(m, n, r, c, v)
+        rowptr, colind, values = spx.from_coo_host(m, n, r, c, v)
+        assert np.array_equal(rowptr, A.rowptr) and np.array_equal(colind, A.colind)
+        assert np.array_equal(values.view(np.uint64), A.values.view(np.uint64))
+        spx.validate_host(m, n, rowptr, colind)
+    assert spx.from_coo_host(2, 4, *cases[1][2:])[2][1] == 0.0
+
+
+def test_host_calls_reject_bad_input(lib):
+    import numpy as np
+    import paper_1302_1078_amd as spx
+    from paper_1302_1078_amd._lib import SPX_ERR_INVALID, SpxError
+    with pytest.raises(SpxError) as e:
+        spx.from_coo_host(3, 3, [0, 3], [0, 1], [1.0, 2.0])
+    assert e.value.status == SPX_ERR_INVALID and b"outside" in lib.spx_last_error()
+    good = (np.array([0, 2, 2, 3]), np.array([0, 2, 1]))
+    spx.validate_host(3, 3, *good)
+    bad = [(np.array([1, 2, 2, 3]), good[1], b"rowptr[0]"),
+           (np.array([0, 2, 2, 4]), good[1], b"rowptr[m]"),
+           (np.array([0, 2, 1, 3]), good[1], b"row 1"),
+           (good[0], np.array([0, 3, 1]), b"colind[1]"),
+           (good[0], np.array([0, -1, 1]), b"colind[1]")]
+    for rp, ci, what in bad:
+        with pytest.raises(SpxError):
+            spx.validate_host(3, 3, rp, ci)
+        assert what in lib.spx_last_error(), what
+    # rowptr[m] = nnz counts against the colind length the caller passes
+    with pytest.raises(SpxError):
+        spx.validate_host(3, 3, good[0], good[1][:2])
+
+
+# The boundary's calls against the scope table's list: each listed call is
+# exported under its listed name, or replaced by the named call(s) (reasons in
+# the design notes): a device assembly and validation beside the host ones,
+# and the per-matrix tuning record carried inside the batch descriptor.
+BOUNDARY_MAP = {
+    "csr_spmv": ["csr_spmv"],
+    "csr_spmm": ["csr_spmm"],
+    "csr_from_coo_host": ["csr_from_coo_host", "csr_from_coo"],
+    "csr_validate_host": ["csr_validate_host", "csr_validate"],
+    "csr_plan_workspace_bytes": ["csr_plan_workspace_bytes"],
+    "csr_plan_create": ["csr_plan_create"],
+    "csr_plan_export_bins": ["csr_plan_export_bins"],
+    "csr_plan_destroy": ["csr_plan_destroy"],
+    "csr_transpose_index": ["csr_transpose_index"],
+    "csr_spmv_t": ["csr_spmv_t"],
+    "csr_sddmm": ["csr_sddmm"],
+    "csr_batch_create": ["csr_batch_create"],
+    "csr_batch_run": ["csr_batch_run"],
+    "csr_batch_destroy": ["csr_batch_destroy"],
+    "spx_last_error": ["spx_last_error"],
+}
+
+
+def test_boundary_covers_the_scope_table(lib):
+    names = set(header_functions())
+    for listed, built in BOUNDARY_MAP.items():
+        for b in built:
+            assert b in names and getattr(lib, b, None) is not None, (listed, b)
+    # spx_tune (variant + thresholds per matrix) is the spx_plan_opts carried
+    # in each spx_csr_desc: csr_batch_create takes no separate host_tunes array
+    from paper_1302_1078_amd import _lib
+    fields = dict(_lib.CsrDesc._fields_)
+    assert fields["opts"] is _lib.PlanOpts
+    assert {"nbins", "upper", "lanes", "split_chunk", "kahan_len"} <= {f for f, _ in _lib.PlanOpts._fields_}
