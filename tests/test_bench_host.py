@@ -59,3 +59,47 @@ def test_source_hash_covers_the_product_sources(monkeypatch, tmp_path):
         assert bench.source_hash() != h0, n
         (csrc / n).write_text(n)
     assert bench.source_hash() == h0
+
+
+def test_host_llc_bytes_reads_sysfs(monkeypatch):
+    """Every distinct L3 (one per shared_cpu_list) is counted once."""
+    files = {
+        "/sys/devices/system/cpu/cpu0/cache/index3/size": "32768K",
+        "/sys/devices/system/cpu/cpu0/cache/index3/shared_cpu_list": "0-1",
+        "/sys/devices/system/cpu/cpu1/cache/index3/size": "32768K",
+        "/sys/devices/system/cpu/cpu1/cache/index3/shared_cpu_list": "0-1",
+        "/sys/devices/system/cpu/cpu2/cache/index3/size": "96M",
+        "/sys/devices/system/cpu/cpu2/cache/index3/shared_cpu_list": "2",
+    }
+    import builtins
+    import io
+    real_open = builtins.open
+
+    def fake_open(path, *a, **kw):
+        if path in files:
+            return io.StringIO(files[path])
+        if str(path).startswith("/sys/devices/system/cpu/"):
+            raise OSError(path)
+        return real_open(path, *a, **kw)
+
+    monkeypatch.setattr(bench.os, "sched_getaffinity", lambda pid: {0, 1, 2, 3})
+    monkeypatch.setattr(builtins, "open", fake_open)
+    assert bench.host_llc_bytes() == (32 << 20) + (96 << 20)
+
+
+def test_cpu_baseline_protocol_small():
+    """The CPU-baseline leg on a small matrix: 2 warm-up + reps timed calls on
+    all threads and on one thread, LLC flushed, and the figures it reports
+    consistent with its own timings."""
+    import spgen
+    coo = spgen.powerlaw(4000, 4000, 2.0, 500, 16.0, seed=0)
+    x = spgen.uniform(coo.n, 0)
+    X = spgen.uniform(coo.n * 4, 1).reshape(coo.n, 4)
+    out = bench.cpu_baseline(coo, x, X, 4, 2 * 1000, 2 * 4000, 2)
+    assert out["kind"] == "oracle" and out["llc_flushed"] is True
+    assert out["repetitions"] == 2 and out["warmup"] == 2
+    assert out["cores"] >= 1 and out["one_thread"]["threads"] == 1
+    for r in (out, out["one_thread"]):
+        assert r["spmv_gflops"] > 0 and r["spmm_gflops"] > 0
+    one = out["one_thread"]
+    assert abs(one["gflops"] - (2000 + 8000) / (one["spmv_ms"] + one["spmm_ms"]) / 1e6) < 1e-9 * one["gflops"]
