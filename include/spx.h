@@ -240,6 +240,23 @@ spx_status csr_csc_value_map(int32_t nnz, const int32_t *perm, int32_t *dest, ui
 spx_status csr_values_to_csc(int32_t nnz, const int32_t *dest, const uint16_t *local, const void *values,
                              spx_dtype vtype, void *staging, void *values_csc, void *stream);
 
+/* csr_values_to_csc without the caller's staging buffer, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  It allocates nothing: the
+ * staging lives in a fixed device array of SPX_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends; its
+ * address on the current device is looked up once, on the first call on that
+ * device.  Same arguments and result as csr_values_to_csc (bitwise).
+ * nnz * sizeof(vtype) above SPX_NOALLOC_SCRATCH_BYTES (6,291,456 FP64,
+ * 12,582,912 FP32 or 25,165,824 BF16 values) returns SPX_ERR_UNSUPPORTED
+ * and launches nothing.  Every call on one GPU shares that GPU's array (no
+ * part of it needs clearing: each call writes every staging slot it reads):
+ * calls that may overlap on one GPU (different streams, or host threads
+ * without ordering) race and must be serialised by the caller. */
+#define SPX_NOALLOC_SCRATCH_BYTES 50331648 /* 48 MiB */
+spx_status csr_values_to_csc_noalloc(int32_t nnz, const int32_t *dest, const uint16_t *local,
+                                     const void *values, spx_dtype vtype, void *values_csc, void *stream);
+
 /* Sampled dot: out[p] = sum_t dY[row(p), t] * X[colind[p], t] for every
  * stored nonzero p (the gradient of y = A(values) x with respect to values).
  * dtype F64 or F32 for dY, X and out alike.  `plan` (nullable) is a plan of

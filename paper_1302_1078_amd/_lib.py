@@ -15,6 +15,7 @@ LIB_PATH = os.environ.get("SPX_LIB") or os.path.join(_PKG, "libspx.so")
 SPX_OK, SPX_ERR_INVALID, SPX_ERR_UNSUPPORTED, SPX_ERR_WORKSPACE, SPX_ERR_HIP = range(5)
 SPX_F64, SPX_F32, SPX_BF16 = 0, 1, 2
 SPX_MAX_BINS = 12
+SPX_NOALLOC_SCRATCH_BYTES = 50331648
 SPX_FLAG_NO_NT_STORE = 1
 SPX_FLAG_SCALAR_X = 2
 SPX_FLAG_NO_XCD_MAP = 4
@@ -100,6 +101,7 @@ SIGNATURES = {
     "csr_csc_value_map_workspace_bytes": (ctypes.c_int, [i32, SZ]),
     "csr_csc_value_map": (ctypes.c_int, [i32, P, P, P, P, ctypes.c_size_t, P]),
     "csr_values_to_csc": (ctypes.c_int, [i32, P, P, P, ctypes.c_int, P, P, P]),
+    "csr_values_to_csc_noalloc": (ctypes.c_int, [i32, P, P, P, ctypes.c_int, P, P]),
     "csr_spmv_t": (ctypes.c_int, [i32, i32, i32, P, P, P, P, P, P, ctypes.c_int, i32, P, i64, P, i64,
                                   ctypes.c_int, i32, P, P]),
     "csr_sddmm": (ctypes.c_int, [i32, i32, i32, P, P, i32, P, i64, P, i64, P, ctypes.c_int, P, P]),

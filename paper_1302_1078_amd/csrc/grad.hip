@@ -4,6 +4,8 @@
 // Rows are visited through the same bin table as the products (row groups of
 // G lanes, or one workgroup per segment of a split row); no cross-lane
 // reduction is needed because every nonzero is independent.
+#include <mutex>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -509,18 +511,12 @@ extern "C" spx_status csr_csc_value_map(int32_t nnz, const int32_t* perm, int32_
   return SPX_OK;
 }
 
-extern "C" spx_status csr_values_to_csc(int32_t nnz, const int32_t* dest, const uint16_t* local,
-                                        const void* values, spx_dtype vtype, void* staging, void* values_csc,
-                                        void* stream) {
-  if (nnz < 0) return fail(SPX_ERR_INVALID, "csr_values_to_csc: negative size");
-  {
-    const spx_status s_nnz = check_nnz(nnz, "csr_values_to_csc");
-    if (s_nnz != SPX_OK) return s_nnz;
-  }
-  if (nnz == 0) return SPX_OK;
-  if (!dest || !local || !values || !staging || !values_csc)
-    return fail(SPX_ERR_INVALID, "csr_values_to_csc: null pointer");
-  hipStream_t st = as_stream(stream);
+namespace spx {
+namespace {
+
+spx_status values_to_csc_impl(const char* who, int32_t nnz, const int32_t* dest, const uint16_t* local,
+                              const void* values, spx_dtype vtype, void* staging, void* values_csc,
+                              hipStream_t st) {
   const unsigned nb = static_cast<unsigned>((static_cast<int64_t>(nnz) + SPX_CSC_BLOCK - 1) / SPX_CSC_BLOCK);
   const int64_t tiles = (static_cast<int64_t>(nnz) + kWG * kStagePerThread - 1) / (kWG * kStagePerThread);
   const unsigned g1 = static_cast<unsigned>((tiles + 7) / 8 * 8);
@@ -543,5 +539,80 @@ extern "C" spx_status csr_values_to_csc(int32_t nnz, const int32_t* dest, const 
   if (vtype == SPX_F32) { SPX_TO_CSC(float) }
   if (vtype == SPX_BF16) { SPX_TO_CSC(uint16_t) }
 #undef SPX_TO_CSC
-  return fail(SPX_ERR_UNSUPPORTED, "csr_values_to_csc: vtype %d", vtype);
+  return fail(SPX_ERR_UNSUPPORTED, "%s: vtype %d", who, vtype);
+}
+
+spx_status values_to_csc_args(const char* who, int32_t nnz, const int32_t* dest, const uint16_t* local,
+                              const void* values, void* values_csc) {
+  if (nnz < 0) return fail(SPX_ERR_INVALID, "%s: negative size", who);
+  const spx_status s_nnz = check_nnz(nnz, who);
+  if (s_nnz != SPX_OK) return s_nnz;
+  if (nnz > 0 && (!dest || !local || !values || !values_csc))
+    return fail(SPX_ERR_INVALID, "%s: null pointer", who);
+  return SPX_OK;
+}
+
+size_t value_bytes(spx_dtype vt) { return vt == SPX_F64 ? 8 : vt == SPX_F32 ? 4 : vt == SPX_BF16 ? 2 : 0; }
+
+// Staging of csr_values_to_csc_noalloc: a fixed device array that every GPU
+// the library runs on holds until the process ends.  Its name is a host-side
+// stand-in in host code; kernels get the device address that
+// hipGetSymbolAddress returns for the current device, resolved once per
+// device (each device has its own copy at its own address).
+__device__ __align__(256) unsigned char scratch[SPX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+spx_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  SPX_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SPX_ERR_UNSUPPORTED, "scratch: device %d beyond the %d the library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(SPX_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPX_OK;
+}
+
+}  // namespace
+}  // namespace spx
+
+extern "C" spx_status csr_values_to_csc(int32_t nnz, const int32_t* dest, const uint16_t* local,
+                                        const void* values, spx_dtype vtype, void* staging, void* values_csc,
+                                        void* stream) {
+  const spx_status s = values_to_csc_args("csr_values_to_csc", nnz, dest, local, values, values_csc);
+  if (s != SPX_OK) return s;
+  if (nnz == 0) return SPX_OK;
+  if (!staging) return fail(SPX_ERR_INVALID, "csr_values_to_csc: null pointer");
+  return values_to_csc_impl("csr_values_to_csc", nnz, dest, local, values, vtype, staging, values_csc,
+                            as_stream(stream));
+}
+
+extern "C" spx_status csr_values_to_csc_noalloc(int32_t nnz, const int32_t* dest, const uint16_t* local,
+                                                const void* values, spx_dtype vtype, void* values_csc,
+                                                void* stream) {
+  const char* who = "csr_values_to_csc_noalloc";
+  spx_status s = values_to_csc_args(who, nnz, dest, local, values, values_csc);
+  if (s != SPX_OK) return s;
+  const size_t vb = value_bytes(vtype);
+  if (vb == 0) return fail(SPX_ERR_UNSUPPORTED, "%s: vtype %d", who, vtype);
+  const size_t need = static_cast<size_t>(nnz) * vb;
+  if (need > static_cast<size_t>(SPX_NOALLOC_SCRATCH_BYTES))
+    return fail(SPX_ERR_UNSUPPORTED,
+                "%s: nnz=%d of %zu-byte values needs %zu bytes of staging, above SPX_NOALLOC_SCRATCH_BYTES=%d "
+                "(use csr_values_to_csc with a caller staging buffer)",
+                who, nnz, vb, need, SPX_NOALLOC_SCRATCH_BYTES);
+  if (nnz == 0) return SPX_OK;
+  void* staging = nullptr;
+  s = scratch_for_current_device(&staging);
+  if (s != SPX_OK) return s;
+  return values_to_csc_impl(who, nnz, dest, local, values, vtype, staging, values_csc, as_stream(stream));
 }
