@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the unflushed (warm) calls, so a kernel trace holds flushed calls only")
     ap.add_argument("--forms", default="c0,c2,c3,c4",
-                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep; rcm = RCM ordering; bcsr = register blocking)")
+                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep; rcm = RCM ordering; bcsr = register blocking; locality = column-locality sweep)")
     ap.add_argument("--form-steps", type=int, default=20)
     return ap.parse_args()
 
@@ -443,6 +443,42 @@ def bench_rcm(ctx, A1=None):
     return out
 
 
+# ---------------------------------------------------------------- locality sweep (Sec. 4.1, 4.2)
+
+def bench_locality(ctx, A1=None):
+    """How the x access pattern sets SpMV speed (the paper's UCLD and
+    actual-versus-application study, Sec. 4.1 and 4.2), over matrices whose
+    column locality differs while their size stays fixed: per matrix the
+    useful cacheline density (128 B lines), the distinct x lines per 256-row
+    tile (a stream tile of the SpMV), the vector access for 8 XCD caches, the
+    flushed FP64 SpMV time, and the flushed time of the index-gather probe
+    with and without the x reads (the x gather alone is their difference).
+    The x-gather L2 hit rate comes from counter runs of the same probe
+    (python -m paper_1302_1078_amd.run --workload locality)."""
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    from paper_1302_1078_amd.run import locality_matrices
+    out = {}
+    for name, A in locality_matrices(torch, spx, spgen, dev):
+        m, n, nnz = A.m, A.n, A.nnz
+        tiles = -(-m // 256)
+        pairs = spx.tile_lines(A, 16, 256)
+        x = torch.from_numpy(spgen.uniform(n, 0)).to(dev)
+        y = torch.empty(m, dtype=torch.float64, device=dev)
+        plan = spx.Plan.for_matrix(A, spx.default_opts(1))
+        fns = [lambda: spx.spmv(A, x, y=y, plan=plan),
+               lambda: spx.ops.probe_index_gather(A.colind, x, gather=True, blocks=4096),
+               lambda: spx.ops.probe_index_gather(A.colind, x, gather=False, blocks=4096)]
+        t = ctx["timer"].run(fns, ctx["fsteps"], 3).mean(axis=0)
+        out[name] = {"m": m, "nnz": nnz, "ucld_line16": spx.ucld(A, 16),
+                     "tile_lines_per_tile": pairs / tiles, "gathers_per_line_in_tile": nnz / pairs,
+                     "vector_access_8xcd": spx.vector_access(A, 16, 8, -(-m // 8)),
+                     "spmv_us": t[0] * 1e6, "spmv_gflops": 2 * nnz / t[0] / 1e9,
+                     "xgather_probe_us": t[1] * 1e6, "colstream_probe_us": t[2] * 1e6}
+        del A, x, y, plan
+        torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------- register blocking (Sec. 4.5)
 
 def bench_bcsr(ctx, A1=None):
@@ -802,6 +838,8 @@ def main():
                     forms[name] = bench_rcm(ctx, A)
                 elif name == "bcsr":
                     forms[name] = bench_bcsr(ctx, A)
+                elif name == "locality":
+                    forms[name] = bench_locality(ctx, A)
                 forms[name]["bench_s"] = round(time.time() - f0, 1)
             except Exception as e:  # a failing form is reported, not hidden
                 forms[name] = {"error": repr(e)}

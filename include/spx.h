@@ -346,6 +346,17 @@ spx_status csr_vector_access(int32_t m, int32_t n, int32_t nnz, const int32_t *h
                              const int32_t *host_colind, int32_t line, int32_t parts, int32_t chunk,
                              double *out);
 
+/* Distinct x cachelines per row tile (Sec. 4.1 and 4.2 count the cachelines
+ * a row's or a core's gathers touch; this is the count for a workgroup that
+ * serves `tile` consecutive rows): *out receives the number of distinct
+ * (tile, x line) pairs over the tiles [t*tile, (t+1)*tile), x line =
+ * column / line.  Divided by the tile count it is the mean distinct lines a
+ * tile gathers; nnz divided by it is the mean number of gathers per line
+ * inside a tile.  Host function on host arrays of a structurally valid
+ * matrix (a column outside [0, n) returns SPX_ERR_INVALID); *out is host. */
+spx_status csr_tile_lines(int32_t m, int32_t n, int32_t nnz, const int32_t *host_rowptr,
+                          const int32_t *host_colind, int32_t line, int32_t tile, int64_t *out);
+
 /* Useful cacheline density (Sec. 4.1): the mean over nonempty rows of
  * L / (line x distinct x cachelines the row touches); columns ascending in
  * each row.  Host function on host arrays; *out is host. */

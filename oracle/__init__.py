@@ -22,6 +22,8 @@ Functions and the passages they follow:
 * ``rel2``           -- ||y_hat - y||_2 / ||y||_2 in FP64, the absolute norm of
   the difference when ||y|| = 0.
 * ``ucld``           -- useful cacheline density (Sec. 4.1).
+* ``tile_lines``     -- distinct x cachelines per tile of consecutive rows
+  (Sec. 4.1 and 4.2's cacheline counting, per workgroup tile).
 * ``degree_order``   -- columns by descending nonzero count, ties ascending
   (a locality ordering set beside the paper's RCM step, Sec. 4.4).
 
@@ -76,6 +78,8 @@ def lib():
         L.orc_ucld.argtypes = [i32, P, P, i32, P]
         L.orc_vector_access.restype = f64
         L.orc_vector_access.argtypes = [i32, i32, P, P, i32, i32, i32]
+        L.orc_tile_lines.restype = ctypes.c_int64
+        L.orc_tile_lines.argtypes = [i32, i32, P, P, i32, i32]
         L.orc_rcm.restype = ctypes.c_int
         L.orc_rcm.argtypes = [i32, i32, P, P, P]
         L.orc_max_threads.restype = ctypes.c_int
@@ -197,6 +201,13 @@ def vector_access(A: CSR, line: int = 16, parts: int = 8, chunk: int = 64) -> fl
     """Expected number of times x is moved from memory (Sec. 4.2): rows dealt
     round-robin to `parts` infinite caches in chunks of `chunk` rows."""
     return float(lib().orc_vector_access(A.m, A.n, _p(A.rowptr), _p(_i32(A.colind)), line, parts, chunk))
+
+
+def tile_lines(A: CSR, line: int = 16, tile: int = 256) -> int:
+    """Distinct (tile, x line) pairs over tiles of `tile` consecutive rows
+    (x line = column // line): the x lines a row tile gathers, summed over
+    tiles (the per-tile form of Sec. 4.1's cacheline counting)."""
+    return int(lib().orc_tile_lines(A.m, A.n, _p(A.rowptr), _p(_i32(A.colind)), line, tile))
 
 
 def rcm(A: CSR) -> np.ndarray:

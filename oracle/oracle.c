@@ -273,6 +273,35 @@ double orc_vector_access(int32_t m, int32_t n, const int32_t *rowptr, const int3
 }
 
 /* ------------------------------------------------------------------------
+ * Distinct x cachelines per row tile (the locality a workgroup sees; the
+ * per-tile form of the paper's cacheline counting, Sec. 4.1 and 4.2): rows
+ * are cut into tiles of `tile` consecutive rows; the result is the number of
+ * distinct (tile, x line) pairs, x line = column / line.  Divided by the
+ * number of tiles it is the mean distinct lines a tile gathers; nnz divided
+ * by it is the mean number of gathers per fetched line inside a tile.
+ * ---------------------------------------------------------------------- */
+int64_t orc_tile_lines(int32_t m, int32_t n, const int32_t *rowptr, const int32_t *colind, int32_t line,
+                       int32_t tile) {
+  int64_t nlines = ((int64_t)n + line - 1) / line;
+  if (nlines == 0 || m == 0) return 0;
+  int64_t *stamp = (int64_t *)calloc((size_t)nlines, sizeof(int64_t));
+  int64_t pairs = 0;
+  for (int64_t t = 0; t * tile < m; ++t) {
+    int64_t r1 = (t + 1) * tile < m ? (t + 1) * tile : m;
+    for (int64_t i = t * tile; i < r1; ++i)
+      for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+        int64_t ln = colind[p] / line;
+        if (stamp[ln] != t + 1) {
+          stamp[ln] = t + 1;
+          ++pairs;
+        }
+      }
+  }
+  free(stamp);
+  return pairs;
+}
+
+/* ------------------------------------------------------------------------
  * Reverse Cuthill-McKee ordering (Sec. 4.4 applies it to every matrix; the
  * algorithm is Cuthill and McKee's breadth-first numbering, reversed).  The
  * paper used MATLAB's implementation and gives no tie rules, so this reading

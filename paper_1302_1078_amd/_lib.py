@@ -117,6 +117,7 @@ SIGNATURES = {
     "csr_permute": (ctypes.c_int, [i32, i32, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]),
     "csr_vector_access": (ctypes.c_int, [i32, i32, i32, P, P, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]),
     "csr_ucld": (ctypes.c_int, [i32, i32, P, P, i32, ctypes.POINTER(ctypes.c_double)]),
+    "csr_tile_lines": (ctypes.c_int, [i32, i32, i32, P, P, i32, i32, ctypes.POINTER(ctypes.c_int64)]),
     "bcsr_workspace_bytes": (ctypes.c_int, [i32, i32, i32, SZ]),
     "csr_bcsr_count": (ctypes.c_int, [i32, i32, i32, P, P, i32, i32, P, P, ctypes.c_size_t, P]),
     "csr_to_bcsr": (ctypes.c_int, [i32, i32, i32, P, P, P, i32, i32, i32, P, P, P, P, P, P, ctypes.c_size_t, P]),

@@ -199,6 +199,30 @@ extern "C" spx_status csr_vector_access(int32_t m, int32_t n, int32_t nnz, const
   return SPX_OK;
 }
 
+extern "C" spx_status csr_tile_lines(int32_t m, int32_t n, int32_t nnz, const int32_t* host_rowptr,
+                                     const int32_t* host_colind, int32_t line, int32_t tile, int64_t* out) {
+  if (m < 0 || n < 0 || nnz < 0 || line < 1 || tile < 1 || !out)
+    return fail(SPX_ERR_INVALID, "csr_tile_lines: bad argument");
+  if (m > 0 && (!host_rowptr || (nnz > 0 && !host_colind)))
+    return fail(SPX_ERR_INVALID, "csr_tile_lines: null pointer");
+  // per tile: the line ids of its nonzeros, sorted, counted once each
+  int64_t pairs = 0;
+  std::vector<int32_t> ids;
+  for (int64_t r0 = 0; r0 < m; r0 += tile) {
+    const int64_t r1 = std::min<int64_t>(r0 + tile, m);
+    ids.clear();
+    for (int32_t p = host_rowptr[r0]; p < host_rowptr[r1]; ++p) {
+      const int32_t c = host_colind[p];
+      if (c < 0 || c >= n) return fail(SPX_ERR_INVALID, "csr_tile_lines: column out of range");
+      ids.push_back(c / line);
+    }
+    std::sort(ids.begin(), ids.end());
+    pairs += std::unique(ids.begin(), ids.end()) - ids.begin();
+  }
+  *out = pairs;
+  return SPX_OK;
+}
+
 extern "C" spx_status csr_ucld(int32_t m, int32_t nnz, const int32_t* host_rowptr, const int32_t* host_colind,
                                int32_t line, double* out) {
   if (m < 0 || nnz < 0 || line < 1 || !out) return fail(SPX_ERR_INVALID, "csr_ucld: bad argument");

@@ -428,6 +428,16 @@ def vector_access(A: CSR, line: int = 16, parts: int = 8, chunk: int = 64) -> fl
     return out.value
 
 
+def tile_lines(A: CSR, line: int = 16, tile: int = 256) -> int:
+    """Distinct (tile, x line) pairs over tiles of `tile` consecutive rows
+    (csr_tile_lines, host): the x lines a workgroup serving those rows gathers."""
+    rp, ci = _host_pattern(A)
+    out = ctypes.c_int64()
+    check(_lib.load().csr_tile_lines(A.m, A.n, A.nnz, _ptr(rp), _ptr(ci), line, tile, ctypes.byref(out)),
+          "csr_tile_lines")
+    return out.value
+
+
 def ucld(A: CSR, line: int = 16) -> float:
     """Useful cacheline density (csr_ucld, host)."""
     rp, ci = _host_pattern(A)

@@ -18,9 +18,11 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c3", "stencil27", "c4"],
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c3", "stencil27", "c4", "locality"],
                     help="c4: the 256-matrix batch (FP32 values, k in {1, 4, 16}); runs the batch "
-                         "and then the same products launched one by one, --reps times each")
+                         "and then the same products launched one by one, --reps times each.  "
+                         "locality: the locality sweep's matrices in turn (locality_matrices), --op "
+                         "xgather / colstream / spmv --reps times on each")
     ap.add_argument("--op", default="spmv", choices=["spmv", "spmm", "xgather", "colstream", "autograd"],
                     help="xgather / colstream: the index-gather probe over the matrix's colind "
                          "(with / without the x reads); autograd: forward + backward through the "
@@ -51,6 +53,9 @@ def main(argv=None):
         return
     if args.workload == "c4":
         batch_vs_single(torch, ops, spgen, dev, args.reps)
+        return
+    if args.workload == "locality":
+        locality_run(torch, ops, spgen, dev, args.op, args.reps, not args.no_flush)
         return
     if args.probe_copy_mib:
         a = torch.zeros(args.probe_copy_mib << 17, dtype=torch.float64, device=dev)
@@ -109,6 +114,53 @@ def main(argv=None):
     torch.cuda.synchronize()
     print(f"ran {args.op} on {args.workload} ({A.m} rows, {A.nnz} nnz, k={k}, {args.dtype}) "
           f"x{args.reps} per plan, {len(plans)} plan(s)", flush=True)
+
+
+LOCALITY = ("powerlaw_col1.6", "powerlaw_col2.0", "powerlaw_col2.0_degree", "powerlaw_col2.4",
+            "stencil27_natural", "stencil27_half_relabeled", "stencil27_relabeled")
+
+
+def locality_matrices(torch, ops, spgen, dev):
+    """The locality sweep (the paper's Sec. 4.1-4.2 study of how the x access
+    pattern sets SpMV speed), one matrix at a time as (name, device CSR), in
+    LOCALITY order: the headline power-law row lengths (1,048,576 square,
+    Zipf 2.0, mean 16) with column laws of exponent 1.6, 2.0 and 2.4, the 2.0
+    matrix in degree order, and the 27-point stencil on 128^3 in natural
+    order, with half of its vertices relabelled at random, and fully
+    relabelled.  FP64 values."""
+    def up(coo):
+        return ops.from_coo(coo.m, coo.n, torch.from_numpy(coo.r).to(dev), torch.from_numpy(coo.c).to(dev),
+                            torch.from_numpy(coo.v).to(dev))
+    for ca in (1.6, 2.0, 2.4):
+        A = up(spgen.powerlaw(1 << 20, 1 << 20, 2.0, 20_000, 16.0, 0, col_alpha=ca))
+        yield f"powerlaw_col{ca}", A
+        if ca == 2.0:
+            yield "powerlaw_col2.0_degree", ops.permute(A, ops.degree_order(A))
+        del A
+    st = spgen.workload_c2_stencil(0)
+    yield "stencil27_natural", up(st)
+    yield "stencil27_half_relabeled", up(spgen.relabeled(st, 1, 0.5))
+    yield "stencil27_relabeled", up(spgen.relabeled(st, 1))
+
+
+def locality_run(torch, ops, spgen, dev, op: str, reps: int, flush: bool):
+    """For counter runs: `op` (xgather, colstream or spmv with the default
+    plan) `reps` times on each locality matrix, in LOCALITY order, each call
+    after a 1 GiB flush."""
+    fb = torch.zeros(1 << 27, dtype=torch.float64, device=dev) if flush else None
+    for name, A in locality_matrices(torch, ops, spgen, dev):
+        x = torch.from_numpy(spgen.uniform(A.n, 0)).to(dev)
+        plan = ops.Plan.for_matrix(A, ops.default_opts(1)) if op == "spmv" else None
+        y = torch.empty(A.m, dtype=torch.float64, device=dev)
+        for _ in range(reps):
+            if fb is not None:
+                ops.probe("flush", fb)
+            if op == "spmv":
+                ops.spmv(A, x, y=y, plan=plan)
+            else:
+                ops.probe_index_gather(A.colind, x, gather=op == "xgather", blocks=4096)
+        torch.cuda.synchronize()
+        print(f"locality {name}: {op} x{reps} ({A.m} rows, {A.nnz} nnz)", flush=True)
 
 
 def batch_vs_single(torch, ops, spgen, dev, reps: int):

@@ -191,12 +191,18 @@ def uniform_rows(m: int, n: int, per_row: int, seed: int = 0, values: str = "uni
 
 
 def powerlaw(m: int, n: int, alpha: float, lmax: int, mean: float, seed: int = 0,
-             values: str = "uniform") -> COO:
-    """Zipf-Mandelbrot row lengths (mean `mean`, max `lmax`) with hot columns of the same law."""
+             values: str = "uniform", col_alpha: float | None = None) -> COO:
+    """Zipf-Mandelbrot row lengths (mean `mean`, max `lmax`) with hot columns of
+    the same law, or of exponent `col_alpha` (same mean and maximum) when given:
+    that changes how skewed the column use is and leaves the row lengths as
+    they are."""
     lmax = int(min(lmax, n))
     q = zm_shift(alpha, lmax, mean)
     lens = zm_lengths(m, alpha, q, lmax, seed, TAG_ROWLEN)
-    w = zm_lengths(n, alpha, q, lmax, seed, TAG_COLW)
+    if col_alpha is None or col_alpha == alpha:
+        w = zm_lengths(n, alpha, q, lmax, seed, TAG_COLW)
+    else:
+        w = zm_lengths(n, col_alpha, zm_shift(col_alpha, lmax, mean), lmax, seed, TAG_COLW)
     off = np.zeros(m, dtype=np.int64)
     if m > 1:
         np.cumsum(lens[:-1], out=off[1:])
@@ -208,7 +214,7 @@ def powerlaw(m: int, n: int, alpha: float, lmax: int, mean: float, seed: int = 0
                                       _p(w), _p(r), _p(c))
     return COO(m, n, r, c, _values(r, c, seed, values, 0.0),
                {"kind": "powerlaw", "alpha": alpha, "lmax": lmax, "mean": mean, "q": q,
-                "draws": int(draws)})
+                "col_alpha": alpha if col_alpha is None else col_alpha, "draws": int(draws)})
 
 
 def stencil5(nx: int, ny: int, seed: int = 0, values: str = "uniform") -> COO:
@@ -243,15 +249,23 @@ def shuffled(coo: COO, seed: int) -> COO:
 
 # ---------------------------------------------------------------- named workloads
 
-def relabeled(coo: COO, seed: int) -> COO:
+def relabeled(coo: COO, seed: int, fraction: float = 1.0) -> COO:
     """Rows and columns renumbered by one seeded random permutation (P A P^T,
     square matrices): a banded matrix loses its band.  Old vertex i becomes
-    label[i]."""
+    label[i].  With fraction < 1 only a seeded random subset of
+    round(fraction * m) vertices is shuffled among its own labels; the others
+    keep theirs."""
     if coo.m != coo.n:
         raise ValueError("relabeling needs a square matrix")
     rng = np.random.Generator(np.random.PCG64(seed))
-    label = rng.permutation(coo.m).astype(np.int32)
-    return COO(coo.m, coo.n, label[coo.r], label[coo.c], coo.v.copy(), dict(coo.info, relabeled=seed))
+    if fraction >= 1.0:
+        label = rng.permutation(coo.m).astype(np.int32)
+    else:
+        label = np.arange(coo.m, dtype=np.int32)
+        moved = np.sort(rng.choice(coo.m, int(round(fraction * coo.m)), replace=False))
+        label[moved] = moved[rng.permutation(moved.size)]
+    return COO(coo.m, coo.n, label[coo.r], label[coo.c], coo.v.copy(),
+               dict(coo.info, relabeled=seed, relabeled_fraction=fraction))
 
 
 def workload_c0(seed: int = 0) -> COO:

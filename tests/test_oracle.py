@@ -626,3 +626,29 @@ def test_bcsr_bytes_match_the_paper():
         S = oracle.csr_from_coo(8, 8, rr.ravel()[pick], cc.ravel()[pick], np.ones(t))
         blocked = oracle.bcsr_bytes(oracle.to_bcsr(S, 8, 8)) - rowptr_bytes
         assert np.sign(12 * t - blocked) == relation, t
+
+
+def test_tile_lines_brute_force_and_closed_forms():
+    """Distinct (tile, x line) pairs: Python sets on random matrices; equal to
+    vector_access with one part per tile (an independent oracle function, so
+    a wrong tile bound or line index in either shows); closed forms for a
+    diagonal and a dense matrix."""
+    rng = np.random.default_rng(61)
+    for m, n, nnz in [(1, 1, 1), (37, 50, 200), (300, 128, 2000), (1000, 5000, 6000)]:
+        r, c, v = rand_coo(rng, m, n, nnz)
+        A = oracle.csr_from_coo(m, n, r, c, v)
+        rows = A.row_of()
+        for line, tile in [(16, 256), (8, 7), (1, 1), (4, 1000)]:
+            expect = len({(int(i) // tile, int(j) // line) for i, j in zip(rows, A.colind)})
+            assert oracle.tile_lines(A, line, tile) == expect
+            tiles = -(-m // tile)
+            nlines = -(-n // line)
+            assert oracle.vector_access(A, line, tiles, tile) * nlines == pytest.approx(expect, rel=1e-15)
+    # diagonal n x n: a tile of T rows (T a multiple of the line L) touches T / L lines
+    n = 4096
+    D = oracle.csr_from_coo(n, n, np.arange(n), np.arange(n), np.ones(n))
+    assert oracle.tile_lines(D, 16, 256) == (n // 256) * (256 // 16)
+    # dense m x n: every tile touches every line
+    F = oracle.csr_from_coo(10, 40, np.repeat(np.arange(10), 40), np.tile(np.arange(40), 10), np.ones(400))
+    assert oracle.tile_lines(F, 16, 3) == 4 * 3
+    assert oracle.tile_lines(oracle.csr_from_coo(0, 5, [], [], []), 16, 4) == 0

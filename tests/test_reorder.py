@@ -64,3 +64,5 @@ def test_metrics_match_oracle(spx, name, coo):
         assert spx.vector_access(H, line, parts, chunk) == oracle.vector_access(A, line, parts, chunk)
     for line in (8, 16):
         assert spx.ucld(H, line) == oracle.ucld(A, line)
+    for line, tile in [(16, 256), (8, 7), (1, 1), (4, 5000)]:
+        assert spx.tile_lines(H, line, tile) == oracle.tile_lines(A, line, tile)

@@ -130,3 +130,27 @@ def test_batch_specs_recipe():
     assert all(s.k in (1, 4, 16) for s in specs)
     rows = np.array([s.rows for s in specs])
     assert rows.min() >= 900 and rows.max() <= 210_000
+
+
+def test_partial_relabel_and_column_law():
+    st = spgen.stencil5(40, 30, 1)
+    half = spgen.relabeled(st, 3, fraction=0.5)
+    full = spgen.relabeled(st, 3)
+    # a relabelling is a bijection of the vertices: the set of (r, c) pairs
+    # maps one to one, so the pair count is unchanged and no pair repeats
+    for h in (half, full):
+        assert np.unique(h.r.astype(np.int64) * h.n + h.c).size == st.nnz
+    # half of the vertices are candidates to move; the rest keep their labels
+    fixed = np.flatnonzero(half.r == st.r)  # entries whose row label did not change
+    assert 0.4 < np.unique(st.r[fixed]).size / st.m < 0.7
+    assert np.array_equal(spgen.relabeled(st, 3, 0.5).r, half.r)  # seeded
+    # the column law changes the column degrees, not the row lengths
+    a = spgen.powerlaw(20_000, 20_000, 2.0, 2_000, 16.0, seed=4)
+    b = spgen.powerlaw(20_000, 20_000, 2.0, 2_000, 16.0, seed=4, col_alpha=1.6)
+    la = np.bincount(a.r, minlength=a.m)
+    lb = np.bincount(b.r, minlength=b.m)
+    assert np.array_equal(la, lb)
+    da = np.sort(np.bincount(a.c, minlength=a.n))[::-1]
+    db = np.sort(np.bincount(b.c, minlength=b.n))[::-1]
+    top = a.n // 100
+    assert db[:top].sum() > da[:top].sum()  # a heavier column tail concentrates more accesses
