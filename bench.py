@@ -29,7 +29,7 @@ The other workloads are reported under detail.forms (skip with --quick):
       oracle)
   c3  differentiation form: 524,288 power-law (mean 20), FP32 forward and
       backward (CSC-index and atomic transpose, sampled dot)
-  c4  batched form: 256 matrices in one persistent launch replayed from a
+  c4  batched form: 256 matrices in one launch per lane layout replayed from a
       HIP graph, autotuned plans, against sequential single-matrix calls
 """
 from __future__ import annotations

@@ -266,15 +266,16 @@ spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, c
                      spx_dtype dtype, const spx_plan *plan, void *stream);
 
 /* ---------------------------------------------------------------- batches
- * Many independent products Y_b <- A_b X_b in one persistent kernel launch
- * per lane layout present (the layout follows from each matrix's k: at most
- * a few launches, whatever the number of matrices).  Each descriptor names
- * one CSR matrix, its right-hand side and its plan options (from an
- * autotuner or spx_plan_default_opts).  csr_batch_create bins every matrix on
- * the device, builds the work-tile list in the caller's workspace and
- * SYNCHRONISES `stream`.  csr_batch_run launches a queue-reset kernel and
- * the persistent kernels on `stream`, capturable into a HIP graph (it uses
- * no memset).  Each matrix's result is bit-identical to
+ * Many independent products Y_b <- A_b X_b in one kernel launch per lane
+ * layout present (the layout follows from each matrix's k: at most a few
+ * launches, whatever the number of matrices).  Each descriptor names one CSR
+ * matrix, its right-hand side and its plan options (from an autotuner or
+ * spx_plan_default_opts).  csr_batch_create bins every matrix on the device,
+ * builds the work-tile list in the caller's workspace (grouped by layout,
+ * heaviest estimated tiles first) and SYNCHRONISES `stream`.  csr_batch_run
+ * launches, on `stream`, one workgroup per tile of each layout's group; it
+ * uses no memset and no atomics outside the split-row reductions, so it can
+ * be captured into a HIP graph.  Each matrix's result is bit-identical to
  * csr_spmm (k > 1) or csr_spmv (k = 1) with a plan created from the same
  * options plus SPX_FLAG_KEEP_STREAM: the batch fills the device as a whole,
  * so it keeps every stream bin as 256-row tiles. */
@@ -294,7 +295,7 @@ spx_status csr_batch_workspace_bytes(int32_t count, const spx_csr_desc *host_des
 spx_status csr_batch_create(int32_t count, const spx_csr_desc *host_descs, void *workspace,
                             size_t ws_bytes, void *stream, spx_batch **out);
 spx_status csr_batch_run(const spx_batch *batch, void *stream);
-/* Tiles, workgroups of the largest persistent launch, and total split segments. */
+/* Tiles, workgroups of the largest per-layout launch, and total split segments. */
 spx_status csr_batch_info(const spx_batch *batch, int64_t *ntiles, int32_t *grid, int64_t *nsegments);
 void csr_batch_destroy(spx_batch *batch);
 

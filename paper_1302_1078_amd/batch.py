@@ -1,11 +1,10 @@
-"""Batched products: many (A_b, X_b) -> Y_b in one persistent launch per
-lane layout.
+"""Batched products: many (A_b, X_b) -> Y_b in one launch per lane layout.
 
 csr_batch_create bins every matrix with its own plan options (from
 ``autotune`` or the defaults) and builds a tile list grouped by layout and
-ordered by cost; each ``run()`` is one reset kernel plus the persistent
-kernels on the current stream, so it can be captured into a HIP graph
-(``capture()``) and replayed.
+ordered by cost (heaviest first); each ``run()`` launches one workgroup per
+tile of each layout on the current stream, so it can be captured into a HIP
+graph (``capture()``) and replayed.
 """
 from __future__ import annotations
 

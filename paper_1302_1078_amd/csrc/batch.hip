@@ -1,19 +1,23 @@
-// batch.hip -- many independent products Y_b <- A_b X_b in a few persistent
-// launches (the paper's motivation: many SpMV/SpMM-based requests served at
-// once, Sec. 1 and Sec. 5).
+// batch.hip -- many independent products Y_b <- A_b X_b in a few launches
+// (the paper's motivation: many SpMV/SpMM-based requests served at once,
+// Sec. 1 and Sec. 5).
 //
 // At creation every matrix is binned with its own plan options (from an
 // autotuner or the defaults) and its row-group tiles are appended to a tile
 // list grouped by lane layout (the (KL, VEC) that its k selects) and, inside
-// a group, ordered by estimated cost (heaviest first).  At run time a reset
-// kernel zeroes the queue heads and one persistent kernel per layout present
-// (a grid of up to CUs x 8 workgroups) pops its group's tiles with an atomic
-// counter until they are gone.  A kernel per layout keeps each launch's
-// register use, and so its occupancy, that of the single-matrix kernel of the
-// same layout (one kernel holding every layout needed over 220 VGPRs, two
-// waves per SIMD).  Each tile runs exactly the row-group code of the
-// single-matrix launch with the matrix's own arguments, so every result is
-// bit-identical to csr_spmv / csr_spmm with the same plan options.
+// a group, ordered by estimated cost (heaviest first).  At run time one
+// kernel per layout present runs one workgroup per tile of its group: tile
+// i of the group goes to workgroup i, so the hardware dispatcher starts the
+// heaviest tiles first and fills each freed slot with the next one (a
+// longest-first schedule with no queue, atomics or reset kernel).  A kernel
+// per layout keeps each launch's register use, and so its occupancy, near
+// that of the single-matrix kernel of the same layout.  A persistent
+// version (a queue of tiles popped by a grid of CUs x 8 workgroups) needed
+// 79-115 VGPRs for the loop around the same tile code, against 60-71 here,
+// and ran at 4-6 instead of 7-8 waves per SIMD.  Each tile runs exactly the
+// row-group code of the single-matrix launch with the matrix's own
+// arguments, so every result is bit-identical to csr_spmv / csr_spmm with
+// the same plan options.
 #include <string.h>
 
 #include <algorithm>
@@ -37,9 +41,7 @@ struct TileDesc {
 
 struct BatchArgs {
   const ProdArgs* mats;
-  const TileDesc* tiles;
-  int32_t ntiles;
-  int32_t* head;
+  const TileDesc* tiles;  // the layout's group of the tile list
 };
 
 // layouts: 0 -> (KL 1, VEC 1); i >= 1 -> (KL 2^(i-1), VEC V)
@@ -89,56 +91,26 @@ __device__ __forceinline__ void run_tile(const ProdArgs& a, const BinDesc& d, in
   }
 }
 
-__global__ void k_batch_reset(int32_t* heads, int n) {
-  if (static_cast<int>(threadIdx.x) < n) heads[threadIdx.x] = 0;
-}
-
-// The loop must stay uniform: its header is a barrier (a convergent operation
-// the compiler cannot duplicate), and every value that steers control flow is
-// made wave-uniform with readfirstlane.  A loop whose header were the
-// `threadIdx.x == 0` pop could be compiled with that branch folded into the
-// back edge, sending lane 0 and the other lanes to different loop headers;
-// under exec masking the other lanes would then re-read the same tile id
-// forever.
-// Tiles are popped in runs of kPop (one atomic per run): with hundreds of
-// thousands of small tiles a single queue head would otherwise serialise
-// the launch on one address.
-constexpr int kPop = 16;
-
-// One persistent launch per lane layout: each instantiation holds only the
-// code of its layout, so its register use (and occupancy) is that of the
-// single-matrix kernel of the same layout.  MR adds the multi-row path of
-// short-row SpMV bins, as in the single-matrix launch.
+// One workgroup per tile of a layout's group (blockIdx.x indexes the group,
+// heaviest tiles first).  The tile's fields are wave-uniform (read through a
+// uniform pointer), so every branch of the tile code is scalar, as in the
+// single-matrix launch.
 template <class C, bool MR>
 __global__ __launch_bounds__(kWG) void k_batch(const BatchArgs b) {
-  __shared__ int32_t next;
-  int32_t id = 0, end = 0;
-  for (;;) {
-    __syncthreads();  // LDS of the previous tile is no longer in use
-    if (id >= end) {  // uniform: id and end are wave-uniform SGPR values
-      if (threadIdx.x == 0) next = atomicAdd(b.head, kPop);
-      __syncthreads();
-      id = __builtin_amdgcn_readfirstlane(next);
-      end = min(id + kPop, b.ntiles);
-      __syncthreads();
-    }
-    if (id >= b.ntiles) break;
-    const TileDesc* tp = b.tiles + id;
-    ++id;
-    const int32_t mat = __builtin_amdgcn_readfirstlane(tp->mat);
-    const int32_t slot = __builtin_amdgcn_readfirstlane(tp->slot);
-    const int32_t tile = __builtin_amdgcn_readfirstlane(tp->tile);
-    const ProdArgs& a = b.mats[mat];
-    BinDesc d;
-    d.blk_begin = 0;
-    d.nblk = __builtin_amdgcn_readfirstlane(a.bins[slot].nblk);
-    d.row_begin = __builtin_amdgcn_readfirstlane(a.bins[slot].row_begin);
-    d.nrows = __builtin_amdgcn_readfirstlane(a.bins[slot].nrows);
-    d.lanes = __builtin_amdgcn_readfirstlane(a.bins[slot].lanes);
-    d.bin = 0;
-    d.rpg = __builtin_amdgcn_readfirstlane(a.bins[slot].rpg);
-    run_tile<C, MR>(a, d, tile);
-  }
+  const TileDesc* tp = b.tiles + blockIdx.x;
+  const int32_t mat = __builtin_amdgcn_readfirstlane(tp->mat);
+  const int32_t slot = __builtin_amdgcn_readfirstlane(tp->slot);
+  const int32_t tile = __builtin_amdgcn_readfirstlane(tp->tile);
+  const ProdArgs& a = b.mats[mat];
+  BinDesc d;
+  d.blk_begin = 0;
+  d.nblk = a.bins[slot].nblk;
+  d.row_begin = a.bins[slot].row_begin;
+  d.nrows = a.bins[slot].nrows;
+  d.lanes = a.bins[slot].lanes;
+  d.bin = 0;
+  d.rpg = a.bins[slot].rpg;
+  run_tile<C, MR>(a, d, tile);
 }
 
 bool pair_ok(spx_dtype vt, spx_dtype xt) {
@@ -153,8 +125,8 @@ int layout_id(int kl, int vec) {
   return id < kLayouts ? id : -1;
 }
 
-// Options as the batch uses them: unpadded bins (the queue, not the XCD map,
-// spreads the tiles) and partials wide enough for the matrix's k.
+// Options as the batch uses them: unpadded bins (the tile list, not the XCD
+// map, orders the work) and partials wide enough for the matrix's k.
 spx_plan_opts batch_opts(const spx_csr_desc& d) {
   spx_plan_opts o = d.opts;
   o.flags |= SPX_FLAG_NO_XCD_MAP;
@@ -172,7 +144,7 @@ int64_t tile_bound(const spx_csr_desc& d, const spx_plan_opts& o) {
 struct BatchLayout {
   std::vector<size_t> plan_off;
   std::vector<size_t> plan_bytes;
-  size_t mats_off, tiles_off, head_off, total;
+  size_t mats_off, tiles_off, total;
   int64_t max_tiles;
 };
 
@@ -195,8 +167,6 @@ spx_status layout_ws(int32_t count, const spx_csr_desc* descs, BatchLayout* L) {
   off = align_up(off + sizeof(ProdArgs) * static_cast<size_t>(count > 0 ? count : 1));
   L->tiles_off = off;
   off = align_up(off + sizeof(TileDesc) * static_cast<size_t>(L->max_tiles + 1));
-  L->head_off = off;
-  off = align_up(off + sizeof(int32_t) * kLayouts);
   L->total = off;
   return SPX_OK;
 }
@@ -224,12 +194,10 @@ struct spx_batch {
   int32_t ntiles;
   int32_t grid;  // workgroups of the largest per-layout launch
   int64_t nseg;
-  int32_t* head;  // one queue head per layout
   spx::ProdArgs* mats;
   spx::TileDesc* tiles;
   int32_t first[spx::kLayouts];  // tiles of layout l: [first[l], first[l] + ntile[l])
   int32_t ntile[spx::kLayouts];
-  int32_t lgrid[spx::kLayouts];
   bool multi_row;  // layout 0 has short-row bins served several rows per group
   std::vector<spx_plan*> plans;
 };
@@ -346,15 +314,7 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
   for (size_t t = 0; t < entries.size(); ++t) tiles[t] = entries[t].td;
   B->mats = reinterpret_cast<ProdArgs*>(base + L.mats_off);
   B->tiles = reinterpret_cast<TileDesc*>(base + L.tiles_off);
-  B->head = reinterpret_cast<int32_t*>(base + L.head_off);
   B->ntiles = static_cast<int32_t>(tiles.size());
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      cus = v;
-  }
-  const int64_t want = static_cast<int64_t>(cus) * 8;
   B->grid = 0;
   for (int l = 0; l < kLayouts; ++l) {
     B->first[l] = 0;
@@ -364,10 +324,7 @@ extern "C" spx_status csr_batch_create(int32_t count, const spx_csr_desc* descs,
     const int l = tiles[t].layout;
     if (B->ntile[l]++ == 0) B->first[l] = static_cast<int32_t>(t);
   }
-  for (int l = 0; l < kLayouts; ++l) {
-    B->lgrid[l] = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(want, B->ntile[l])));
-    if (B->ntile[l] > 0) B->grid = std::max(B->grid, B->lgrid[l]);
-  }
+  for (int l = 0; l < kLayouts; ++l) B->grid = std::max(B->grid, B->ntile[l]);
   hipError_t e = hipMemcpyAsync(B->mats, mats.data(), sizeof(ProdArgs) * count, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpyAsync(B->tiles, tiles.data(), sizeof(TileDesc) * tiles.size(), hipMemcpyHostToDevice, st);
@@ -382,8 +339,8 @@ namespace {
 
 template <typename VT, typename XT, int V>
 spx_status launch_layout(const spx_batch* B, int l, hipStream_t st) {
-  const BatchArgs a{B->mats, B->tiles + B->first[l], B->ntile[l], B->head + l};
-  const unsigned g = static_cast<unsigned>(B->lgrid[l]);
+  const BatchArgs a{B->mats, B->tiles + B->first[l]};
+  const unsigned g = static_cast<unsigned>(B->ntile[l]);
   switch (l) {
     case 0:
       if (B->multi_row) k_batch<Cfg<VT, XT, 1, 1>, true><<<g, kWG, 0, st>>>(a);
@@ -407,8 +364,6 @@ extern "C" spx_status csr_batch_run(const spx_batch* B, void* stream) {
   if (!B) return fail(SPX_ERR_INVALID, "csr_batch_run: batch is null");
   if (B->ntiles == 0) return SPX_OK;
   hipStream_t st = as_stream(stream);
-  k_batch_reset<<<1, 64, 0, st>>>(B->head, kLayouts);
-  SPX_LAUNCHED("k_batch_reset");
   for (int l = 0; l < kLayouts; ++l) {
     if (B->ntile[l] == 0) continue;
     spx_status s;

@@ -51,18 +51,18 @@ def main(argv=None):
     if args.bandwidth:
         bandwidth(torch, ops, dev)
         return
-    if args.workload == "c4":
-        batch_vs_single(torch, ops, spgen, dev, args.reps)
-        return
-    if args.workload == "locality":
-        locality_run(torch, ops, spgen, dev, args.op, args.reps, not args.no_flush)
-        return
     if args.probe_copy_mib:
         a = torch.zeros(args.probe_copy_mib << 17, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         ops.probe("copy", a, b)
         torch.cuda.synchronize()
         del a, b
+    if args.workload == "c4":
+        batch_vs_single(torch, ops, spgen, dev, args.reps)
+        return
+    if args.workload == "locality":
+        locality_run(torch, ops, spgen, dev, args.op, args.reps, not args.no_flush)
+        return
     coo = {"c0": lambda: spgen.workload_c0(0), "c1": lambda: spgen.workload_c1(0),
            "c3": lambda: spgen.workload_c3(0), "stencil27": lambda: spgen.workload_c2_stencil(0)}[args.workload]()
     A = ops.from_coo(coo.m, coo.n, torch.from_numpy(coo.r).to(dev), torch.from_numpy(coo.c).to(dev),

@@ -1,4 +1,4 @@
-"""Batched persistent launch: each matrix's result must be bit-identical to the
+"""Batched launches: each matrix's result must be bit-identical to the
 single-matrix launch with the same plan options (identical per-row
 arithmetic), within the FP bound of the oracle, and stable under HIP-graph
 replay."""
