@@ -271,6 +271,15 @@ def bench_c2(ctx, A1=None):
                 b = app_bytes(m, n, nnz, k, sv, sx)
                 r = {"us": t * 1e6, "gflops": 2 * nnz * k / t / 1e9, "eff_gbs": b / t / 1e9,
                      "frac_hbm": b / t / 1e9 / PEAK_HBM_GBS, "bytes": b}
+                if k > 1 and name.startswith("stencil"):
+                    # the staged plan (row tiles' X windows in LDS), an opt-in
+                    # alternative for banded matrices, on the same data
+                    ps = spx.Plan.staged(Aq, k, Xd.dtype)
+                    ys = torch.empty_like(yd)
+                    ts = float(ctx["timer"].run([lambda: spx.spmm(Aq, Xd, Y=ys, plan=ps)], ctx["fsteps"], 3)[:, 0].mean())
+                    r["staged_plan"] = {"us": ts * 1e6, "eff_gbs": b / ts / 1e9, "frac_hbm": b / ts / 1e9 / PEAK_HBM_GBS,
+                                        "speedup_vs_default_plan": t / ts, **ps.staged_info()}
+                    del ps, ys
                 if vname != "f64":
                     r["rel2_vs_gpu_fp64"] = max(rel2(yh[:, j], y3[:, j]) for j in range(k))
                     y5 = fp64_product(A.with_values(vals.double()), Xq64, k)

@@ -180,6 +180,33 @@ spx_status csr_plan_export_bins(const spx_plan *plan, int32_t *host_row_perm, in
 spx_status csr_plan_info(const spx_plan *plan, int32_t *nbins, int32_t *nsplit_rows, int32_t *nsegments);
 void csr_plan_destroy(spx_plan *plan);
 
+/* Staged plan for SpMM (Sec. 5's reuse of X rows by rows that share
+ * columns): rows are cut into tiles of R consecutive rows, R = min(128 / L,
+ * 64) with L the lanes that cover one X row at this k and X type; for each
+ * tile the plan stores the sorted list of the columns its nonzeros touch
+ * and, per nonzero, the 16-bit index of its column in that list.  A product
+ * through the plan runs one workgroup per tile, copies the tile's X rows
+ * (its window), values, indices and row offsets into LDS in one round of
+ * vector loads, and computes from there.  A tile with more than 2,048
+ * nonzeros or a window above 32 KB gathers X from memory instead, with the
+ * same per-row arithmetic.  Built on the device from rowptr and colind
+ * (columns need not be sorted), in the caller's workspace
+ * (csr_plan_staged_workspace_bytes), which must stay allocated and
+ * unmodified while the plan is used; SYNCHRONISES `stream`.  Serves csr_spmm
+ * with exactly this k and X type, and X, Y that allow 16-byte loads
+ * (16-byte aligned, ldx and ldy multiples of the vector); other calls return
+ * SPX_ERR_UNSUPPORTED, as do csr_spmv_t, csr_sddmm and
+ * csr_plan_export_bins.  k in [2, 128], a multiple of the 16-byte vector (2
+ * FP64 or 4 FP32 elements); xtype F64 or F32 (the X / Y type). */
+spx_status csr_plan_staged_workspace_bytes(int32_t m, int32_t n, int32_t nnz, int32_t k, spx_dtype xtype,
+                                           size_t *bytes);
+spx_status csr_plan_create_staged(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr,
+                                  const int32_t *colind, int32_t k, spx_dtype xtype, void *workspace,
+                                  size_t ws_bytes, void *stream, spx_plan **out);
+/* Rows per tile, tiles, tiles staged in LDS, and the largest window (X rows). */
+spx_status csr_plan_staged_info(const spx_plan *plan, int32_t *tile_rows, int32_t *ntiles, int32_t *nstaged,
+                                int32_t *max_cols);
+
 /* ---------------------------------------------------------------- products
  * y <- A x.  vtype/xytype pairs: (F64, F64) plain FP64; (F32, F32) and
  * (BF16, F32) reduced-precision values with FP32 vectors.  x has n entries,

@@ -53,8 +53,11 @@ bool pair_ok(spx_dtype vt, spx_dtype xt) {
          (vt == SPX_BF16 && xt == SPX_F32);
 }
 
-spx_status check_plan(const spx_plan* plan, int32_t rows, int32_t nnz, int32_t k, const char* who) {
+spx_status check_plan(const spx_plan* plan, int32_t rows, int32_t nnz, int32_t k, const char* who,
+                      bool staged_ok = true) {
   if (!plan) return SPX_OK;
+  if (plan->staged && !staged_ok)
+    return fail(SPX_ERR_UNSUPPORTED, "%s: a staged plan serves csr_spmv / csr_spmm only", who);
   if (plan->m != rows || plan->nnz != nnz)
     return fail(SPX_ERR_INVALID, "%s: plan built for %d rows / %d nonzeros, called with %d / %d", who,
                 plan->m, plan->nnz, rows, nnz);
@@ -96,6 +99,10 @@ spx_status product(const char* who, int32_t m, int32_t n, int32_t nnz, const int
   a.k = k;
   int kl, vec;
   layout_for_k(k, xt, X, a.ldx, Y, a.ldy, plan ? plan->opts.flags : 0u, &kl, &vec);
+  if (plan && plan->staged) {
+    if (vperm) return fail(SPX_ERR_UNSUPPORTED, "%s: a staged plan serves CSR-order values only", who);
+    return launch_staged(a, plan, m, vt, xt, kl, vec, as_stream(stream));
+  }
   if (plan) bins_from_plan(plan, a, kl, true);
   else bins_unbinned(m, nnz, kl, a);
   return launch_product(a, vt, xt, kl, vec, as_stream(stream));
@@ -154,7 +161,7 @@ extern "C" spx_status csr_spmv_t(int32_t m, int32_t n, int32_t nnz, const int32_
   if (m > 0 && !rowptr) return fail(SPX_ERR_INVALID, "csr_spmv_t: rowptr is null");
   if (nnz > 0 && (!colind || !values || !dY))
     return fail(SPX_ERR_INVALID, "csr_spmv_t: null colind, values or dY");
-  spx_status s = check_plan(plan, m, nnz, 1, "csr_spmv_t");
+  spx_status s = check_plan(plan, m, nnz, 1, "csr_spmv_t", false);
   if (s != SPX_OK) return s;
   ProdArgs a;
   memset(&a, 0, sizeof(a));
@@ -185,7 +192,7 @@ extern "C" spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t
   if (m == 0 || nnz == 0) return SPX_OK;
   if (!rowptr || !colind || !dY || !X || !out)
     return fail(SPX_ERR_INVALID, "csr_sddmm: null pointer");
-  spx_status s = check_plan(plan, m, nnz, 1, "csr_sddmm");
+  spx_status s = check_plan(plan, m, nnz, 1, "csr_sddmm", false);
   if (s != SPX_OK) return s;
   ProdArgs a;
   memset(&a, 0, sizeof(a));

@@ -135,6 +135,21 @@ struct spx_plan {
   int32_t* seg_first;                 // device, [nsplit + 1]
   int32_t* counters;                  // device, [nsplit]
   double* partials;                   // device, [nseg * max_k]
+  // X staging (csr_plan_create_staged; zero for a binned plan): rows in tiles
+  // of tile_rows consecutive rows, each tile's distinct X rows staged in LDS
+  int32_t staged;                     // 1 for a staged plan
+  int32_t k;                          // right-hand sides the windows were sized for
+  int32_t xtype;                      // spx_dtype of X / Y
+  int32_t kl, vec;                    // lane layout of the product (lanes per X row, elements per lane)
+  int32_t tile_rows;                  // rows per tile (kWG / kl)
+  int32_t ntiles;
+  int32_t nstaged;                    // tiles whose window is staged (the rest gather directly)
+  int32_t max_cols;                   // largest staged window, in X rows
+  int32_t max_nnz;                    // most nonzeros in a staged tile
+  int32_t* tile_cols;                 // device, [ntiles]: window size, or -1 (direct gathers)
+  int32_t* tile_off;                  // device, [ntiles + 1]: offset of the tile's column list
+  int32_t* tcols;                     // device: the tiles' sorted distinct columns, concatenated
+  uint16_t* loc;                      // device, [nnz]: window index of each nonzero of a staged tile
 };
 
 namespace spx {
@@ -150,6 +165,9 @@ int lanes_valid(int lanes);
 // Lanes per X row (KL) and elements per lane (VEC) for k right-hand sides.
 void layout_for_k(int32_t k, spx_dtype xt, const void* X, int64_t ldx, const void* Y, int64_t ldy,
                   uint32_t flags, int* kl, int* vec);
+// Product through a staged plan (staged.hip).
+spx_status launch_staged(ProdArgs& a, const spx_plan* plan, int32_t m, int vt, int xt, int kl, int vec,
+                         hipStream_t st);
 // Backward traversals (grad.hip).
 spx_status launch_scatter_t(ProdArgs& a, const spx_plan* plan, int32_t m, int32_t n, int32_t nnz,
                             int vt, int xt, hipStream_t st);

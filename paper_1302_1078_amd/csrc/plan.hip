@@ -363,6 +363,7 @@ extern "C" spx_status csr_plan_create(int32_t m, int32_t n, int32_t nnz, const i
 extern "C" spx_status csr_plan_export_bins(const spx_plan* p, int32_t* host_row_perm,
                                            int32_t* host_bin_off) {
   if (!p) return fail(SPX_ERR_INVALID, "csr_plan_export_bins: plan is null");
+  if (p->staged) return fail(SPX_ERR_INVALID, "csr_plan_export_bins: a staged plan has no bins");
   if (host_bin_off)
     for (int b = 0; b <= p->opts.nbins; ++b) host_bin_off[b] = p->bin_off[b];
   if (host_row_perm && p->m > 0)

@@ -181,6 +181,33 @@ class Plan:
     def for_matrix(cls, A: CSR, opts: PlanOpts | None = None, k: int = 1) -> "Plan":
         return cls(A.rowptr, A.m, A.n, A.nnz, opts if opts is not None else default_opts(k, A.values.dtype))
 
+    @classmethod
+    def staged(cls, A: CSR, k: int, xdtype=torch.float64) -> "Plan":
+        """Staged plan (csr_plan_create_staged): tiles of consecutive rows whose
+        X windows are copied into LDS, for SpMM with exactly this k and X type."""
+        L = _lib.load()
+        _dev(A.rowptr, A.colind)
+        xt = _lib.SPX_F64 if xdtype == torch.float64 else _lib.SPX_F32
+        self = cls.__new__(cls)
+        self.opts = default_opts(k, A.values.dtype)
+        self.m, self.n, self.nnz = A.m, A.n, A.nnz
+        nb = ctypes.c_size_t()
+        check(L.csr_plan_staged_workspace_bytes(A.m, A.n, A.nnz, k, xt, ctypes.byref(nb)),
+              "csr_plan_staged_workspace_bytes")
+        self.workspace = _workspace(nb.value, A.device)
+        h = ctypes.c_void_p()
+        check(L.csr_plan_create_staged(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), k, xt,
+                                       _ptr(self.workspace), nb.value, _stream(), ctypes.byref(h)),
+              "csr_plan_create_staged")
+        self.handle = h
+        return self
+
+    def staged_info(self) -> dict:
+        a, b, c, d = (ctypes.c_int32() for _ in range(4))
+        check(_lib.load().csr_plan_staged_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                               ctypes.byref(d)), "csr_plan_staged_info")
+        return {"tile_rows": a.value, "tiles": b.value, "staged_tiles": c.value, "max_window_rows": d.value}
+
     def export_bins(self):
         import numpy as np
         nb = self.opts.nbins

@@ -7,7 +7,8 @@ assembled by the oracle itself; nothing it reads comes from the GPU.
       FP64 SpMV and SpMM (k = 16).
   C2  27-point stencil on 128^3 (55.7 M nonzeros) and the C1 power-law
       matrix: SpMV (k = 1) and SpMM (k = 8, 32) with FP64, FP32 and BF16
-      values, every element against the oracle.
+      values, every element against the oracle; the stencil's SpMM also
+      through the staged plan the benchmark reports beside the default.
   C3  power-law 524,288 rows, FP32: one autograd forward and backward
       (y, dx = A^T dy, dvalues).
   C4  the 256-matrix batch with autotuned plans, replayed from a HIP graph.
@@ -102,7 +103,7 @@ def oracle_product(A, X):
 U_VALUE = {"f32": U32, "bf16": 2.0 ** -8 + U32 + 2.0 ** -8 * U32}
 
 
-def check_precision_form(spx, torch, A, G, k, what):
+def check_precision_form(spx, torch, A, G, k, what, staged=False):
     """The precision form in the benchmark's launch configuration (default
     plan of each value type) against the oracle, every output element:
       f64          per-row bound and rel2 <= 1e-12 against the FP64 oracle;
@@ -128,7 +129,7 @@ def check_precision_form(spx, torch, A, G, k, what):
             Gv, Xd = G.with_values(G.values.to(torch.bfloat16)), dev(torch, Xq)
             wide = spgen.bf16_bits_to_f64(spgen.to_bf16_bits(A.values))
         opts = spx.default_opts(k, Gv.values.dtype)
-        plan = spx.Plan.for_matrix(Gv, opts)
+        plan = spx.Plan.staged(Gv, k, Xd.dtype) if staged else spx.Plan.for_matrix(Gv, opts)
         if k == 1:
             y = spx.spmv(Gv, Xd[:, 0].contiguous(), plan=plan).double().cpu().numpy()[:, None]
         else:
@@ -153,6 +154,12 @@ def check_precision_form(spx, torch, A, G, k, what):
 def test_c2_stencil_precisions(spx, torch, c2_stencil, k):
     A, G = c2_stencil
     check_precision_form(spx, torch, A, G, k, "C2 27-point 128^3")
+
+
+@pytest.mark.parametrize("k", [8, 32])
+def test_c2_stencil_precisions_staged(spx, torch, c2_stencil, k):
+    A, G = c2_stencil
+    check_precision_form(spx, torch, A, G, k, "C2 27-point 128^3, staged plan", staged=True)
 
 
 @pytest.mark.parametrize("k", [1, 8, 32])
