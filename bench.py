@@ -28,7 +28,9 @@ The other workloads are reported under detail.forms (skip with --quick):
       only in the CPU-baseline leg; the tests hold these products to the
       oracle)
   c3  differentiation form: 524,288 power-law (mean 20), FP32 forward and
-      backward (CSC-index and atomic transpose, sampled dot)
+      backward (CSC-index and atomic transpose, sampled dot gathering x or
+      streaming the forward's saved gather), and the autograd step with and
+      without the saved gather
   c4  batched form: 256 matrices in one launch per lane layout replayed from a
       HIP graph, autotuned plans, against sequential single-matrix calls
 """
@@ -539,6 +541,7 @@ def bench_c3(ctx):
     y = torch.empty(m, dtype=torch.float32, device=dev)
     dx = torch.empty(n, dtype=torch.float32, device=dev)
     dv = torch.empty(nnz, dtype=torch.float32, device=dev)
+    xg = torch.empty(nnz, dtype=torch.float32, device=dev)
     vstage = torch.empty_like(A.values)
     vcsc = torch.empty_like(A.values)
     Acsc = A.with_values(vcsc)
@@ -552,27 +555,38 @@ def bench_c3(ctx):
            lambda: spx.spmv_t(A, dy, mode=1, plan=plan, out=dx),
            lambda: spx.sddmm(A, dy, x, plan=plan, out=dv),
            dx_csc_values,
-           lambda: spx.values_to_csc(A.values, g0.vmap, staging=vstage, out=vcsc)]
+           lambda: spx.values_to_csc(A.values, g0.vmap, staging=vstage, out=vcsc),
+           lambda: spx.spmv_save(A, x, y=y, xsave=xg, plan=plan),
+           lambda: spx.sddmm_saved(A, dy, xg, plan=plan, out=dv)]
     t = ctx["timer"].run(fns, ctx["fsteps"], 3).mean(axis=0)
     fwd_b = app_bytes(m, n, nnz, 1, 4, 4)
     csc_b = 4 * nnz * 3 + 4 * (n + 1) + 4 * m + 4 * n     # perm, rowind, values + colptr, dy, dx
     atom_b = 8 * nnz + 4 * (m + 1) + 4 * m + 2 * 4 * n    # colind, values, rowptr, dy, dx zero+write
     sdd_b = 8 * nnz + 4 * (m + 1) + 4 * m + 4 * n         # colind, out, rowptr, dy, x
-    # autograd round trip through the Function
+    sdds_b = 8 * nnz + 4 * (m + 1) + 4 * m                # saved x, out, rowptr, dy
+    # autograd round trip through the Function, with the forward's gathered
+    # x kept for the sampled dot (the default) and without
     v = A.values.clone().requires_grad_(True)
     xt = x.clone().requires_grad_(True)
+    g1 = spx.GradContext(A, mode=0, save_gather=False)
 
-    def step():
-        yy = spx.spmv_autograd(v, xt, g0)
-        yy.backward(dy)
-    ta = float(ctx["timer"].run([step], 10, 2)[:, 0].mean())
+    def step(g):
+        def f():
+            v.grad = xt.grad = None   # gradients set to None between steps, as zero_grad() does
+            yy = spx.spmv_autograd(v, xt, g)
+            yy.backward(dy)
+        return f
+    ta = ctx["timer"].run([step(g0), step(g1)], 10, 2).mean(axis=0)
     return {"workload": "power-law 524,288 x 524,288, Zipf(2.0) mean 20, FP32", "nnz": nnz,
             "forward_us": t[0] * 1e6, "forward_eff_gbs": fwd_b / t[0] / 1e9,
             "dx_csc_us": t[1] * 1e6, "dx_csc_eff_gbs": csc_b / t[1] / 1e9,
             "dx_csc_values_moved_us": t[4] * 1e6, "values_to_csc_us": t[5] * 1e6,
             "dx_atomic_us": t[2] * 1e6, "dx_atomic_eff_gbs": atom_b / t[2] / 1e9,
             "dvalues_us": t[3] * 1e6, "dvalues_eff_gbs": sdd_b / t[3] / 1e9,
-            "autograd_fwd_bwd_us": ta * 1e6,
+            "forward_save_us": t[6] * 1e6, "forward_save_eff_gbs": (fwd_b + 4 * nnz) / t[6] / 1e9,
+            "dvalues_saved_us": t[7] * 1e6, "dvalues_saved_eff_gbs": sdds_b / t[7] / 1e9,
+            "autograd_fwd_bwd_us": float(ta[0]) * 1e6,
+            "autograd_fwd_bwd_no_saved_gather_us": float(ta[1]) * 1e6,
             "note": "gradients are checked in tests/test_gpu_forms.py (gradcheck, FD, dense reference)"}
 
 

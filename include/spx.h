@@ -292,6 +292,27 @@ spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, c
                      int32_t k, const void *dY, int64_t lddy, const void *X, int64_t ldx, void *out,
                      spx_dtype dtype, const spx_plan *plan, void *stream);
 
+/* y <- A x as csr_spmv (same arguments, plans and bitwise the same y), and
+ * also xsave[p] = x[colind[p]] for every stored nonzero p: nnz elements of
+ * xytype, written in CSR order (device memory of the caller).  The sampled
+ * dot of a later backward can then read that operand as a stream
+ * (csr_sddmm_saved) instead of gathering x again: nnz x sizeof(xytype) more
+ * bytes written here, a random gather fewer there.  A staged plan is
+ * rejected (SPX_ERR_UNSUPPORTED); xsave == NULL with nnz > 0 is
+ * SPX_ERR_INVALID.  Asynchronous on `stream`. */
+spx_status csr_spmv_save(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                         const void *values, spx_dtype vtype, const void *x, void *y, spx_dtype xytype,
+                         void *xsave, const spx_plan *plan, void *stream);
+
+/* Sampled dot from a saved gather (k = 1): out[p] = dy[row(p)] * xsave[p]
+ * for every stored nonzero p, with xsave from csr_spmv_save.  Bitwise equal
+ * to csr_sddmm(k = 1) with the x that was saved.  dtype F64 or F32 for dy,
+ * xsave and out alike; dy has m entries, xsave and out nnz.  `plan`
+ * (nullable, not staged) is a plan of the CSR pattern and only sets the
+ * traversal.  Asynchronous on `stream`. */
+spx_status csr_sddmm_saved(int32_t m, int32_t nnz, const int32_t *rowptr, const void *dy, const void *xsave,
+                           void *out, spx_dtype dtype, const spx_plan *plan, void *stream);
+
 /* ---------------------------------------------------------------- batches
  * Many independent products Y_b <- A_b X_b in one kernel launch per lane
  * layout present (the layout follows from each matrix's k: at most a few

@@ -7,5 +7,6 @@ library raises.
 from ._lib import PlanOpts, SpxError, missing_symbols  # noqa: F401
 from .ops import (BCSR, CSR, CSCIndex, CSCValueMap, Plan, bcsr_spmv, csc_value_map, default_opts,  # noqa: F401
                   degree_order, from_coo, from_coo_host, permute, validate_host, values_to_csc,
-                  probe, rcm, sddmm, spmm, spmv, spmv_t, tile_lines, transpose_index, ucld, validate, vector_access, version)
+                  probe, rcm, sddmm, sddmm_saved, spmm, spmv, spmv_save, spmv_t, tile_lines,
+                  transpose_index, ucld, validate, vector_access, version)
 from .autograd import GradContext, SpMVFunction, spmv_autograd  # noqa: F401

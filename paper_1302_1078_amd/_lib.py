@@ -108,6 +108,8 @@ SIGNATURES = {
     "csr_spmv_t": (ctypes.c_int, [i32, i32, i32, P, P, P, P, P, P, ctypes.c_int, i32, P, i64, P, i64,
                                   ctypes.c_int, i32, P, P]),
     "csr_sddmm": (ctypes.c_int, [i32, i32, i32, P, P, i32, P, i64, P, i64, P, ctypes.c_int, P, P]),
+    "csr_spmv_save": (ctypes.c_int, [i32, i32, i32, P, P, P, ctypes.c_int, P, P, ctypes.c_int, P, P, P]),
+    "csr_sddmm_saved": (ctypes.c_int, [i32, i32, P, P, P, P, ctypes.c_int, P, P]),
     "csr_batch_workspace_bytes": (ctypes.c_int, [i32, ctypes.POINTER(CsrDesc), SZ]),
     "csr_batch_create": (ctypes.c_int, [i32, ctypes.POINTER(CsrDesc), P, ctypes.c_size_t, P, PP]),
     "csr_batch_run": (ctypes.c_int, [P, P]),

@@ -2,6 +2,10 @@
 
 Forward: csr_spmv / csr_spmm.  Backward (both on the GPU through the C ABI):
   d values[p] = dY[row(p), :] . X[colind[p], :]   (csr_sddmm, sampled dot)
+When the values need a gradient and x is a vector, the forward runs
+csr_spmv_save, which also stores every gathered x[colind[p]]; the sampled dot
+then streams that copy (csr_sddmm_saved, bitwise the same result) instead of
+gathering x a second time, for nnz more elements written and kept.
   d X         = A^T dY                            (csr_spmv_t: CSC-index gather,
                                                    or atomic scatter)
 With the CSC index (mode 0) and csc_values, the values are first moved to CSC
@@ -14,8 +18,8 @@ from __future__ import annotations
 
 import torch
 
-from .ops import (CSCIndex, CSR, Plan, csc_value_map, default_opts, sddmm, spmm, spmv, spmv_t, transpose_index,
-                  values_to_csc)
+from .ops import (CSCIndex, CSR, Plan, csc_value_map, default_opts, sddmm, sddmm_saved, spmm, spmv, spmv_save,
+                  spmv_t, transpose_index, values_to_csc)
 
 
 class GradContext:
@@ -23,11 +27,14 @@ class GradContext:
     plans of the CSC pattern (for the deterministic transpose).  Plans are
     kept per number of right-hand sides k (a plan with split rows serves
     products up to its max_k), so a 2-D X of any width gets a plan built for
-    it on first use; `k` only picks the plans built up front."""
+    it on first use; `k` only picks the plans built up front.  `save_gather`
+    lets a vector forward keep its gathered operand for the sampled dot."""
 
-    def __init__(self, A: CSR, mode: int = 0, plans: bool = True, k: int = 1, csc_values: bool = True):
+    def __init__(self, A: CSR, mode: int = 0, plans: bool = True, k: int = 1, csc_values: bool = True,
+                 save_gather: bool = True):
         self.A = A
         self.mode = mode
+        self.save_gather = save_gather
         self.plans = plans
         self._fwd = {}
         self._csc = {}
@@ -70,7 +77,10 @@ class SpMVFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, values: torch.Tensor, x: torch.Tensor, gctx: GradContext):
         A = gctx.A.with_values(values)
-        if x.dim() == 1:
+        ctx.xsave = None
+        if x.dim() == 1 and gctx.save_gather and ctx.needs_input_grad[0]:
+            y, ctx.xsave = spmv_save(A, x, plan=gctx.plan_for(1))
+        elif x.dim() == 1:
             y = spmv(A, x, plan=gctx.plan_for(1))
         else:
             y = spmm(A, x, plan=gctx.plan_for(x.shape[1]))
@@ -85,7 +95,10 @@ class SpMVFunction(torch.autograd.Function):
         A = g.A.with_values(values)
         dy = dy.contiguous()
         dvalues = dx = None
-        if ctx.needs_input_grad[0]:
+        if ctx.needs_input_grad[0] and ctx.xsave is not None:
+            dvalues = sddmm_saved(A, dy, ctx.xsave, plan=g.plan_for(1))
+            ctx.xsave = None
+        elif ctx.needs_input_grad[0]:
             dvalues = sddmm(A, dy, x, plan=g.plan)
         if ctx.needs_input_grad[1]:
             dx = g.transpose(A, dy)

@@ -69,7 +69,7 @@ spx_status check_plan(const spx_plan* plan, int32_t rows, int32_t nnz, int32_t k
 spx_status product(const char* who, int32_t m, int32_t n, int32_t nnz, const int32_t* rowptr,
                    const int32_t* colind, const void* values, const int32_t* vperm, spx_dtype vt,
                    int32_t k, const void* X, int64_t ldx, void* Y, int64_t ldy, spx_dtype xt,
-                   const spx_plan* plan, void* stream) {
+                   const spx_plan* plan, void* stream, void* xsave = nullptr) {
   if (m < 0 || n < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "%s: negative size", who);
   {
     const spx_status s_nnz = check_nnz(nnz, who);
@@ -105,6 +105,10 @@ spx_status product(const char* who, int32_t m, int32_t n, int32_t nnz, const int
   }
   if (plan) bins_from_plan(plan, a, kl, true);
   else bins_unbinned(m, nnz, kl, a);
+  if (xsave) {
+    a.xsave = xsave;
+    return launch_product_save(a, vt, xt, as_stream(stream));
+  }
   return launch_product(a, vt, xt, kl, vec, as_stream(stream));
 }
 
@@ -123,6 +127,17 @@ extern "C" spx_status csr_spmv(int32_t m, int32_t n, int32_t nnz, const int32_t*
                                void* stream) {
   return product("csr_spmv", m, n, nnz, rowptr, colind, values, nullptr, vtype, 1, x, 1, y, 1,
                  xytype, plan, stream);
+}
+
+extern "C" spx_status csr_spmv_save(int32_t m, int32_t n, int32_t nnz, const int32_t* rowptr,
+                                    const int32_t* colind, const void* values, spx_dtype vtype,
+                                    const void* x, void* y, spx_dtype xytype, void* xsave,
+                                    const spx_plan* plan, void* stream) {
+  if (nnz > 0 && !xsave) return fail(SPX_ERR_INVALID, "csr_spmv_save: xsave is null");
+  if (plan && plan->staged)
+    return fail(SPX_ERR_UNSUPPORTED, "csr_spmv_save: a staged plan serves csr_spmv / csr_spmm only");
+  return product("csr_spmv_save", m, n, nnz, rowptr, colind, values, nullptr, vtype, 1, x, 1, y, 1,
+                 xytype, plan, stream, nnz > 0 ? xsave : nullptr);
 }
 
 extern "C" spx_status csr_spmm(int32_t m, int32_t n, int32_t nnz, const int32_t* rowptr,
@@ -204,5 +219,31 @@ extern "C" spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t
   a.ldx2 = (k == 1) ? 1 : ldx;
   a.Y = out;
   a.k = k;
-  return launch_sddmm(a, plan, m, nnz, dtype, ldx, as_stream(stream));
+  return launch_sddmm(a, plan, m, nnz, dtype, false, as_stream(stream));
+}
+
+extern "C" spx_status csr_sddmm_saved(int32_t m, int32_t nnz, const int32_t* rowptr, const void* dy,
+                                      const void* xsave, void* out, spx_dtype dtype, const spx_plan* plan,
+                                      void* stream) {
+  if (m < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_sddmm_saved: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_sddmm_saved");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
+  if (dtype != SPX_F64 && dtype != SPX_F32)
+    return fail(SPX_ERR_UNSUPPORTED, "csr_sddmm_saved: dtype must be F64 or F32");
+  if (m == 0 || nnz == 0) return SPX_OK;
+  if (!rowptr || !dy || !xsave || !out) return fail(SPX_ERR_INVALID, "csr_sddmm_saved: null pointer");
+  spx_status s = check_plan(plan, m, nnz, 1, "csr_sddmm_saved", false);
+  if (s != SPX_OK) return s;
+  ProdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.rowptr = rowptr;
+  a.X = dy;
+  a.ldx = 1;
+  a.X2 = xsave;
+  a.ldx2 = 1;
+  a.Y = out;
+  a.k = 1;
+  return launch_sddmm(a, plan, m, nnz, dtype, true, as_stream(stream));
 }

@@ -1,6 +1,9 @@
 // grad.hip -- per-nonzero traversals for the backward of y = A(values) x:
 //   mode kScatterT: dX[colind[p], :] += values[p] * dY[row(p), :] (atomic)
 //   mode kSddmm:    out[p] = sum_t dY[row(p), t] * X[colind[p], t]
+//   mode kSddmmSaved (k = 1): out[p] = dY[row(p)] * xg[p], with xg[p] the
+//                   x[colind[p]] that the forward stored (the save variant of
+//                   the SpMV): the same products, read as a stream
 // Rows are visited through the same bin table as the products (row groups of
 // G lanes, or one workgroup per segment of a split row); no cross-lane
 // reduction is needed because every nonzero is independent.
@@ -13,7 +16,7 @@ namespace spx {
 
 namespace {
 
-enum { kScatterT = 0, kSddmm = 1 };
+enum { kScatterT = 0, kSddmm = 1, kSddmmSaved = 2 };
 
 // The nonzeros p, p + step, ... < p1 of one row, kVisit at a time: the index
 // (and value) loads of a round are issued before any gather, and the gathers
@@ -31,7 +34,7 @@ __device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_
 #pragma unroll
     for (int u = 0; u < kVisit; ++u) {
       h[u] = p + u * step < p1;
-      c[u] = h[u] ? ld_stream(a.colind + p + u * step) : 0;
+      c[u] = (h[u] && MODE != kSddmmSaved) ? ld_stream(a.colind + p + u * step) : 0;
     }
     if constexpr (MODE == kScatterT) {
       XT v[kVisit];
@@ -48,10 +51,13 @@ __device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_
       }
     } else {
       const XT* X2 = static_cast<const XT*>(a.X2);
-      if (a.k == 1) {
+      if (MODE == kSddmmSaved || a.k == 1) {
         XT xr[kVisit];
 #pragma unroll
-        for (int u = 0; u < kVisit; ++u) xr[u] = h[u] ? X2[static_cast<int64_t>(c[u]) * a.ldx2] : XT(0);
+        for (int u = 0; u < kVisit; ++u) {
+          if constexpr (MODE == kSddmmSaved) xr[u] = h[u] ? ld_stream(X2 + p + u * step) : XT(0);
+          else xr[u] = h[u] ? X2[static_cast<int64_t>(c[u]) * a.ldx2] : XT(0);
+        }
 #pragma unroll
         for (int u = 0; u < kVisit; ++u) {
           XT s = XT(0);
@@ -142,7 +148,7 @@ __device__ __forceinline__ void visit_stream(const ProdArgs& a, const BinDesc& d
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       p[u] = s_p0[lo[u]] + (p[u] - s_off[lo[u]]);
-      c[u] = ld_stream(a.colind + p[u]);
+      c[u] = (MODE != kSddmmSaved) ? ld_stream(a.colind + p[u]) : 0;
     }
     if constexpr (MODE == kScatterT) {
       XT v[kPer];
@@ -155,7 +161,10 @@ __device__ __forceinline__ void visit_stream(const ProdArgs& a, const BinDesc& d
     } else {
       XT xr[kPer];
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) xr[u] = static_cast<const XT*>(a.X2)[static_cast<int64_t>(c[u]) * a.ldx2];
+      for (int u = 0; u < kPer; ++u) {
+        if constexpr (MODE == kSddmmSaved) xr[u] = ld_stream(static_cast<const XT*>(a.X2) + p[u]);
+        else xr[u] = static_cast<const XT*>(a.X2)[static_cast<int64_t>(c[u]) * a.ldx2];
+      }
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         XT s = XT(0);
@@ -265,18 +274,20 @@ spx_status launch_scatter_t(ProdArgs& a, const spx_plan* plan, int32_t m, int32_
   return SPX_OK;
 }
 
-spx_status launch_sddmm(ProdArgs& a, const spx_plan* plan, int32_t m, int32_t nnz, int dt,
-                        int64_t ldx, hipStream_t st) {
+spx_status launch_sddmm(ProdArgs& a, const spx_plan* plan, int32_t m, int32_t nnz, int dt, bool saved,
+                        hipStream_t st) {
   grad_bins(plan, m, nnz, a);
-  (void)ldx;
   int64_t grid = 0;
   for (int i = 0; i < a.nbins; ++i) grid = a.bins[i].blk_begin + a.bins[i].nblk;
   if (grid == 0) return SPX_OK;
   const unsigned g = static_cast<unsigned>(grid);
-  if (dt == SPX_F64) k_grad<double, double, kSddmm><<<g, kWG, 0, st>>>(a);
+  if (saved && a.k != 1) return fail(SPX_ERR_INVALID, "csr_sddmm_saved: k must be 1");
+  if (dt == SPX_F64 && saved) k_grad<double, double, kSddmmSaved><<<g, kWG, 0, st>>>(a);
+  else if (dt == SPX_F32 && saved) k_grad<float, float, kSddmmSaved><<<g, kWG, 0, st>>>(a);
+  else if (dt == SPX_F64) k_grad<double, double, kSddmm><<<g, kWG, 0, st>>>(a);
   else if (dt == SPX_F32) k_grad<float, float, kSddmm><<<g, kWG, 0, st>>>(a);
   else return fail(SPX_ERR_UNSUPPORTED, "csr_sddmm: dtype must be F64 or F32");
-  SPX_LAUNCHED("k_grad<sddmm>");
+  SPX_LAUNCHED(saved ? "k_grad<sddmm_saved>" : "k_grad<sddmm>");
   return SPX_OK;
 }
 

@@ -100,8 +100,9 @@ struct ProdArgs {
   const void* X;
   void* Y;
   int64_t ldx, ldy;
-  const void* X2;  // sampled dot: the second dense operand (n x k)
+  const void* X2;  // sampled dot: the second dense operand (n x k), or the saved gather
   int64_t ldx2;
+  void* xsave;     // SpMV with save: x[colind[p]] is also stored at xsave[p] (XT)
   int32_t k;
   int32_t kahan_len;
   const int32_t* row_perm;   // null = identity order
@@ -155,6 +156,7 @@ struct spx_plan {
 namespace spx {
 // Launch one fused product over a prepared bin table (product.hip).
 spx_status launch_product(ProdArgs& a, int vt, int xt, int kl, int vec, hipStream_t st);
+spx_status launch_product_save(ProdArgs& a, int vt, int xt, hipStream_t st);
 // Fill a ProdArgs bin table from a plan, or from the unbinned heuristic.
 // `own_launch`: the table drives a launch of its own (not a tile list shared
 // with other matrices), so a stream bin too small to fill the device is
@@ -171,6 +173,6 @@ spx_status launch_staged(ProdArgs& a, const spx_plan* plan, int32_t m, int vt, i
 // Backward traversals (grad.hip).
 spx_status launch_scatter_t(ProdArgs& a, const spx_plan* plan, int32_t m, int32_t n, int32_t nnz,
                             int vt, int xt, hipStream_t st);
-spx_status launch_sddmm(ProdArgs& a, const spx_plan* plan, int32_t m, int32_t nnz, int dt,
-                        int64_t ldx, hipStream_t st);
+spx_status launch_sddmm(ProdArgs& a, const spx_plan* plan, int32_t m, int32_t nnz, int dt, bool saved,
+                        hipStream_t st);
 }  // namespace spx

@@ -1,7 +1,8 @@
 // product.hip -- fused, row-binned CSR products on gfx950:
 //   y <- A x  (SpMV, paper Sec. 3)        and        Y <- A X  (SpMM, Sec. 5)
-// plus the same traversal for the transpose gather (CSC index) and the
-// sampled dot (gradient with respect to the values).
+// plus the same traversal for the transpose gather (CSC index), and an SpMV
+// variant that also stores each gathered x[colind[p]] at position p for the
+// gradient with respect to the values.
 //
 // One launch covers every bin of a plan.  Workgroups [bins[i].blk_begin,
 // bins[i+1].blk_begin) serve bin i; long-row bins come first so that their
@@ -134,7 +135,30 @@ spx_status launch_vt(ProdArgs& a, int kl, int vec, unsigned grid, hipStream_t st
   return fail(SPX_ERR_UNSUPPORTED, "no product kernel for KL=%d VEC=%d", kl, vec);
 }
 
+// SpMV that keeps its gathered operand (a.xsave): the KL = VEC = 1 kernel
+// compiled with the stores, so that the plain product carries none of them.
+template <typename VT, typename XT>
+spx_status launch_save(ProdArgs& a, unsigned grid, hipStream_t st) {
+  bool mr = false;
+  for (int i = 0; i < a.nbins; ++i) mr = mr || (a.bins[i].rpg > 1);
+  if (mr) return launch_k<Cfg<VT, XT, 1, 1, true>, true>(a, grid, st);
+  return launch_k<Cfg<VT, XT, 1, 1, true>, false>(a, grid, st);
+}
+
 }  // namespace
+
+spx_status launch_product_save(ProdArgs& a, int vt, int xt, hipStream_t st) {
+  if (a.k != 1 || !a.xsave) return fail(SPX_ERR_INVALID, "saved gather: k must be 1 and xsave set");
+  int64_t grid = 0;
+  for (int i = 0; i < a.nbins; ++i) grid = a.bins[i].blk_begin + a.bins[i].nblk;
+  if (grid == 0) return SPX_OK;
+  if (grid > 0x7fffffff) return fail(SPX_ERR_UNSUPPORTED, "grid too large");
+  const unsigned g = static_cast<unsigned>(grid);
+  if (vt == SPX_F64 && xt == SPX_F64) return launch_save<double, double>(a, g, st);
+  if (vt == SPX_F32 && xt == SPX_F32) return launch_save<float, float>(a, g, st);
+  if (vt == SPX_BF16 && xt == SPX_F32) return launch_save<uint16_t, float>(a, g, st);
+  return fail(SPX_ERR_UNSUPPORTED, "unsupported value/vector dtype pair (%d, %d)", vt, xt);
+}
 
 spx_status launch_product(ProdArgs& a, int vt, int xt, int kl, int vec, hipStream_t st) {
   int64_t grid = 0;

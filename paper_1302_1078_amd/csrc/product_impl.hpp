@@ -21,7 +21,10 @@ constexpr int kUnroll = SPX_UNROLL;
 #define SPX_UNROLL_MM 4
 #endif
 
-template <typename VT_, typename XT_, int KL_, int VEC_>
+// SAVE_: SpMV that also stores every gathered x[colind[p]] at xsave[p], so
+// that the gradient with respect to the values (out[p] = dy[row(p)] x[colind[p]])
+// can stream the operand instead of gathering it again.
+template <typename VT_, typename XT_, int KL_, int VEC_, bool SAVE_ = false>
 struct Cfg {
   using VT = VT_;  // stored value type: double, float or uint16_t (bf16 bits)
   using XT = XT_;  // vector / dense type: double or float
@@ -33,6 +36,8 @@ struct Cfg {
   // their lines (see ld_mat)
   static constexpr bool kNT = (KL_ * VEC_ == 1);
   static constexpr int U = (KL_ * VEC_ == 1) ? kUnroll : SPX_UNROLL_MM;
+  static constexpr bool kSave = SAVE_;
+  static_assert(!SAVE_ || KL_ * VEC_ == 1, "the saved gather is an SpMV (k = 1) feature");
   // look-ahead past a row's end is at most U x 256 slots (SPX_MAX_NNZ headroom)
   static_assert(U >= 1 && U * kWG <= 4096, "unroll depth");
 };
@@ -73,6 +78,14 @@ __device__ __forceinline__ typename C::XT value_at(const ProdArgs& a, int32_t p)
   const int32_t q = a.vperm ? ld_mat<C::kNT>(a.vperm + p) : p;
   return static_cast<typename C::XT>(
       ValueLoad<typename C::VT>::template get<C::kNT>(static_cast<const typename C::VT*>(a.values) + q));
+}
+
+// The gathered x[colind[p]] of nonzero p, kept for the backward (save variant).
+template <class C>
+__device__ __forceinline__ void save_x(const ProdArgs& a, int32_t p, typename C::XT x) {
+  typename C::XT* dst = static_cast<typename C::XT*>(a.xsave) + p;
+  if (a.flags & SPX_FLAG_NO_NT_STORE) *dst = x;
+  else __builtin_nontemporal_store(x, dst);
 }
 
 // Accumulate the nonzeros p = p0 + slot, p0 + slot + S, ... < p1 of one row
@@ -138,6 +151,11 @@ __device__ __forceinline__ void accumulate(const ProdArgs& a, int32_t p0, int32_
 #pragma unroll
         for (int e = 0; e < VEC; ++e) xv[u][e] = XT(0);
       }
+    }
+    if constexpr (C::kSave) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (h[u]) save_x<C>(a, p + u * S, xv[u][0]);
     }
     if (!C::kComp || !comp) {
 #pragma unroll
@@ -259,6 +277,11 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
           for (int e = 0; e < VEC; ++e) xv[j][e] = XT(0);
         }
       }
+      if constexpr (C::kSave) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (has[j]) save_x<C>(a, p0[j] + slot, xv[j][0]);
+      }
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         const bool comp = C::kComp && (p1[j] - p0[j] > a.kahan_len);
@@ -281,6 +304,7 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
             const XT vv = value_at<C>(a, p);
             XT xx[VEC];
             load_x<XT, VEC>(X + static_cast<int64_t>(ld_mat<C::kNT>(a.colind + p)) * a.ldx, xx);
+            if constexpr (C::kSave) save_x<C>(a, p, xx[0]);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
               if (C::kComp && comp) cacc[e].add_prod(vv, xx[e]);
@@ -436,7 +460,13 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   // compiler wait for it at once); their products are never summed.
   using VL = ValueLoad<typename C::VT>;
   using Raw = typename VL::Raw;
-  auto fetch = [&](int32_t base, int32_t (&cc)[kStreamPer], Raw (&vv)[kStreamPer]) {
+  // The save variant needs each element's position again when it stores the
+  // gathered x; it keeps the row found by the search (an index below 256)
+  // packed four to a register rather than the positions themselves.
+  static_assert(kStreamPer % 4 == 0 && kStreamRows <= 256, "row indices packed as bytes");
+  constexpr int kPack = kStreamPer / 4;
+  auto fetch = [&](int32_t base, int32_t (&cc)[kStreamPer], Raw (&vv)[kStreamPer],
+                   uint32_t (&rows)[kPack]) {
     int32_t jj[kStreamPer], pp[kStreamPer];
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u) jj[u] = min(base + u * kWG + t, total - 1);
@@ -455,6 +485,12 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
       }
 #pragma unroll
       for (int u = 0; u < kStreamPer; ++u) pp[u] = s_p0[lo[u]] + (jj[u] - s_off[lo[u]]);
+      if constexpr (C::kSave) {
+#pragma unroll
+        for (int i = 0; i < kPack; ++i)
+          rows[i] = static_cast<uint32_t>(lo[4 * i]) | (static_cast<uint32_t>(lo[4 * i + 1]) << 8) |
+                    (static_cast<uint32_t>(lo[4 * i + 2]) << 16) | (static_cast<uint32_t>(lo[4 * i + 3]) << 24);
+      }
     }
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u) {
@@ -466,18 +502,30 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   };
   // software pipeline: the next chunk's colind / values are in flight while
   // the current chunk gathers x and reduces through LDS
+  // (row indices rA / rB: save variant only)
   int32_t cA[kStreamPer];
   Raw vA[kStreamPer];
-  if (total > 0) fetch(0, cA, vA);
+  uint32_t rA[kPack];
+  if (total > 0) fetch(0, cA, vA, rA);
   for (int32_t base = 0; base < total; base += kStreamChunk) {
     const bool more = base + kStreamChunk < total;
     int32_t cB[kStreamPer];
     Raw vB[kStreamPer];
-    if (more) fetch(base + kStreamChunk, cB, vB);
+    uint32_t rB[kPack];
+    if (more) fetch(base + kStreamChunk, cB, vB, rB);
     XT xv[kStreamPer];
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u)
       xv[u] = (base + u * kWG + t < total) ? X[static_cast<int64_t>(cA[u]) * a.ldx] : XT(0);
+    if constexpr (C::kSave) {
+#pragma unroll
+      for (int u = 0; u < kStreamPer; ++u) {
+        const int32_t j = base + u * kWG + t;
+        if (j >= total) continue;
+        const int r = (rA[u / 4] >> (8 * (u % 4))) & 255;
+        save_x<C>(a, contig ? P0 + j : s_p0[r] + (j - s_off[r]), xv[u]);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u) s_prod[u * kWG + t] = static_cast<XT>(VL::widen(vA[u])) * xv[u];
     __syncthreads();
@@ -492,6 +540,8 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
         cA[u] = cB[u];
         vA[u] = vB[u];
       }
+#pragma unroll
+      for (int i = 0; i < kPack; ++i) rA[i] = rB[i];
     }
   }
   if (!active) return;

@@ -260,6 +260,31 @@ def spmv(A: CSR, x: torch.Tensor, y: torch.Tensor | None = None, plan: Plan | No
     return y
 
 
+def spmv_save(A: CSR, x: torch.Tensor, y: torch.Tensor | None = None, xsave: torch.Tensor | None = None,
+              plan: Plan | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """y <- A x, keeping xsave[p] = x[colind[p]] (nnz entries of x's dtype)
+    for sddmm_saved.  Returns (y, xsave)."""
+    L = _lib.load()
+    _dev(A.rowptr, x)
+    _contig(x)
+    if x.numel() < A.n:
+        raise ValueError(f"x has {x.numel()} entries, A has {A.n} columns")
+    if y is None:
+        y = torch.empty(A.m, dtype=x.dtype, device=x.device)
+    if xsave is None:
+        xsave = torch.empty(A.nnz, dtype=x.dtype, device=x.device)
+    _contig(y)
+    _contig(xsave)
+    if y.numel() < A.m or y.dtype != x.dtype:
+        raise ValueError("y must hold m entries of x's dtype")
+    if xsave.numel() < A.nnz or xsave.dtype != x.dtype:
+        raise ValueError("xsave must hold nnz entries of x's dtype")
+    check(L.csr_spmv_save(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(A.values),
+                          dtype_code(A.values), _ptr(x), _ptr(y), dtype_code(x), _ptr(xsave), _plan_ptr(plan),
+                          _stream()), "csr_spmv_save")
+    return y, xsave
+
+
 def spmm(A: CSR, X: torch.Tensor, Y: torch.Tensor | None = None, plan: Plan | None = None) -> torch.Tensor:
     """Y <- A X with X (n x k) and Y (m x k) row-major (unit column stride)."""
     L = _lib.load()
@@ -386,6 +411,25 @@ def sddmm(A: CSR, dY: torch.Tensor, X: torch.Tensor, plan: Plan | None = None,
     check(L.csr_sddmm(A.m, A.n, A.nnz, _ptr(A.rowptr), _ptr(A.colind), k, _ptr(dY),
                       1 if vec else dY.stride(0), _ptr(X), 1 if vec else X.stride(0), _ptr(out),
                       dtype_code(dY), _plan_ptr(plan), _stream()), "csr_sddmm")
+    return out
+
+
+def sddmm_saved(A: CSR, dy: torch.Tensor, xsave: torch.Tensor, plan: Plan | None = None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """out[p] = dy[row(p)] * xsave[p], with xsave from spmv_save (k = 1):
+    bitwise sddmm(A, dy, x) for the x that was saved."""
+    L = _lib.load()
+    _dev(A.rowptr, dy, xsave)
+    _contig(dy)
+    _contig(xsave)
+    if dy.dim() != 1 or dy.numel() < A.m or xsave.numel() < A.nnz or xsave.dtype != dy.dtype:
+        raise ValueError("dy must be a vector of m entries and xsave hold nnz entries of its dtype")
+    if out is None:
+        out = torch.empty(A.nnz, dtype=dy.dtype, device=dy.device)
+    if out.numel() < A.nnz or not out.is_contiguous():
+        raise ValueError("out must hold nnz entries")
+    check(L.csr_sddmm_saved(A.m, A.nnz, _ptr(A.rowptr), _ptr(dy), _ptr(xsave), _ptr(out), dtype_code(dy),
+                            _plan_ptr(plan), _stream()), "csr_sddmm_saved")
     return out
 
 

@@ -298,3 +298,112 @@ def test_autograd_c3_submatrix_gradcheck_f64(spx, torch, mode):
     for inp in (x, X):
         assert torch.autograd.gradcheck(lambda vv, xx: spx.spmv_autograd(vv, xx, g), (v, inp),
                                         eps=1.0, atol=1e-8, rtol=1e-8, fast_mode=True, nondet_tol=nondet)
+
+
+# ---------------------------------------------------------------- saved gather
+
+def save_plans(spx, torch, vdtype):
+    """Plans that reach every SpMV traversal the save variant stores from:
+    none (unbinned row groups), the default binning, kept stream tiles,
+    multi-row groups (rows of at most 4 nonzeros, 4 per 4-lane group), one
+    workgroup per row, and split rows."""
+    t = torch.float64 if vdtype == "f64" else torch.float32
+    return [("none", None),
+            ("default", spx.default_opts(1, t)),
+            ("default-stream", keep_stream(spx.default_opts(1, t))),
+            ("multi-row", spx.PlanOpts.from_dict({"nbins": 3, "upper": [4, 64], "lanes": [4, 64, 0],
+                                                  "split_chunk": 256, "kahan_len": 256, "max_k": 1})),
+            ("block", single_bin_opts(256)),
+            ("split", single_bin_opts(0, chunk=256)),
+            ("wave+split", two_bin_opts(300, 64, chunk=512))]
+
+
+@pytest.mark.parametrize("kind", ["uniform", "powerlaw", "stencil27", "empty_rows", "one_long_row", "tall",
+                                  "wide"])
+@pytest.mark.parametrize("vdtype", ["f64", "f32", "bf16"])
+def test_spmv_save_and_sddmm_saved(spx, torch, kind, vdtype):
+    """The save variant gives bitwise the product of csr_spmv and stores
+    exactly x[colind[p]]; the sampled dot read from it is bitwise the gathering
+    one and the oracle's single rounded product dy[row(p)] x[colind[p]]."""
+    A = matrix(kind, seed=41)
+    x = spgen.uniform(A.n, 42)
+    dy = spgen.normal(A.m, 43)
+    if vdtype == "f64":
+        G = to_gpu(A)
+        xs, dys = x, dy
+        ref = oracle.sddmm(A, dy[:, None], x[:, None])
+    else:
+        G, _ = quantised(A, vdtype, torch)
+        xs, dys = spgen.to_f32(x), spgen.to_f32(dy)
+        # the product of two FP32 numbers is exact in FP64, so rounding it once
+        # to FP32 is the kernel's single FP32 multiplication
+        ref = oracle.sddmm(A, dys.astype(np.float64)[:, None], xs.astype(np.float64)[:, None]).astype(np.float32)
+    xd, dyd = dev(torch, xs), dev(torch, dys)
+    gathered = xs[A.colind]
+    for name, opts in save_plans(spx, torch, vdtype):
+        plan = None if opts is None else spx.Plan.for_matrix(G, opts)
+        y, xsave = spx.spmv_save(G, xd, plan=plan)
+        y0 = spx.spmv(G, xd, plan=plan)
+        assert torch.equal(y.view(torch.int8), y0.view(torch.int8)), (kind, vdtype, name)
+        assert np.array_equal(xsave.cpu().numpy().view(np.uint8), gathered.view(np.uint8)), (kind, vdtype, name)
+        out = spx.sddmm_saved(G, dyd, xsave, plan=plan)
+        out0 = spx.sddmm(G, dyd, xd, plan=plan)
+        assert torch.equal(out.view(torch.int8), out0.view(torch.int8)), (kind, vdtype, name)
+        assert np.array_equal(out.cpu().numpy().view(np.uint8), ref.view(np.uint8)), (kind, vdtype, name)
+
+
+def test_saved_gather_edges_and_misuse(spx, torch):
+    from paper_1302_1078_amd import _lib
+    L = _lib.load()
+    # empty matrix, and rows without nonzeros only
+    for m, n in [(0, 4), (5, 3)]:
+        A = oracle.csr_from_coo(m, n, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        G = to_gpu(A)
+        y, xsave = spx.spmv_save(G, dev(torch, spgen.uniform(n, 1)))
+        assert xsave.numel() == 0 and (y.cpu().numpy() == 0).all()
+        assert spx.sddmm_saved(G, dev(torch, spgen.uniform(m, 2)), xsave).numel() == 0
+    A = matrix("powerlaw", seed=44)
+    G = to_gpu(A)
+    x = dev(torch, spgen.uniform(A.n, 45))
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda:0")
+    # null xsave with nonzeros present
+    st = L.csr_spmv_save(A.m, A.n, A.nnz, G.rowptr.data_ptr(), G.colind.data_ptr(), G.values.data_ptr(),
+                         _lib.SPX_F64, x.data_ptr(), y.data_ptr(), _lib.SPX_F64, None, None, None)
+    assert st == _lib.SPX_ERR_INVALID
+    # a staged plan has no saved-gather variant
+    S = to_gpu(matrix("stencil27", seed=2))
+    with pytest.raises(spx.SpxError):
+        spx.spmv_save(S, dev(torch, spgen.uniform(S.n, 1)), plan=spx.Plan.staged(S, 8))
+    # dtype rules of the sampled dot
+    _, xsave = spx.spmv_save(G, x)
+    out = torch.empty(A.nnz, dtype=torch.float64, device="cuda:0")
+    dy = dev(torch, spgen.normal(A.m, 46))
+    st = L.csr_sddmm_saved(A.m, A.nnz, G.rowptr.data_ptr(), dy.data_ptr(), xsave.data_ptr(), out.data_ptr(),
+                           _lib.SPX_BF16, None, None)
+    assert st == _lib.SPX_ERR_UNSUPPORTED
+    st = L.csr_sddmm_saved(A.m, A.nnz, G.rowptr.data_ptr(), dy.data_ptr(), None, out.data_ptr(),
+                           _lib.SPX_F64, None, None)
+    assert st == _lib.SPX_ERR_INVALID
+    with pytest.raises(ValueError):
+        spx.sddmm_saved(G, dy.float(), xsave)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_autograd_saved_gather_bitwise(spx, torch, dtype):
+    """Gradients with and without the saved gather agree bit for bit on the
+    differentiation workload's 2,000-row submatrix (mode 0, deterministic)."""
+    A = c3_submatrix()
+    t = torch.float64 if dtype == "f64" else torch.float32
+    G = spx.CSR(dev(torch, A.rowptr), dev(torch, A.colind), dev(torch, A.values).to(t), (A.m, A.n))
+    x = dev(torch, spgen.uniform(A.n, 7)).to(t)
+    dy = dev(torch, spgen.normal(A.m, 8)).to(t)
+    grads = []
+    for save in (True, False):
+        g = spx.GradContext(G, mode=0, save_gather=save)
+        v = G.values.clone().requires_grad_(True)
+        xt = x.clone().requires_grad_(True)
+        y = spx.spmv_autograd(v, xt, g)
+        y.backward(dy)
+        grads.append((y.detach(), v.grad, xt.grad))
+    for a, b in zip(*grads):
+        assert torch.equal(a.view(torch.int8), b.view(torch.int8))
