@@ -717,6 +717,23 @@ def cpu_baseline(coo1, xh, Xh, k, flops_v, flops_m, reps):
     ro = oracle.csr_from_coo(coo1.m, coo1.n, coo1.r, coo1.c, coo1.v)  # the oracle's own assembly
     threads = oracle.max_threads()
     flush = HostFlush(len(os.sched_getaffinity(0)))
+    try:
+        runs, spent = _cpu_runs(ro, xh, Xh, flush, threads, flops_v, flops_m, reps)
+    finally:
+        flush.close()   # the flush threads end with the baseline; bench.py starts no process
+    return {"value": runs["all"]["gflops"], "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"the headline matrix ({ro.nnz:,} nonzeros), SpMV + SpMM k={k}, FP64; 2 warm-up + "
+                      f"{reps} timed repetitions on {threads} threads and on 1 thread, each call after a "
+                      f"host LLC flush ({flush.bytes >> 20} MiB touched, 2x the {flush.llc >> 20} MiB of L3); "
+                      f"{spent:.1f} s in total",
+            "llc_flushed": True, "repetitions": reps, "warmup": 2,
+            "spmv_gflops": runs["all"]["spmv_gflops"], "spmm_gflops": runs["all"]["spmm_gflops"],
+            "one_thread": runs["one_thread"]}
+
+
+def _cpu_runs(ro, xh, Xh, flush, threads, flops_v, flops_m, reps):
+    import numpy as np
+    import oracle
     c0 = time.perf_counter()
     runs = {}
     for label, nth in (("all", threads), ("one_thread", 1)):
@@ -737,16 +754,7 @@ def cpu_baseline(coo1, xh, Xh, k, flops_v, flops_m, reps):
         runs[label] = {"threads": nth, "gflops": (flops_v + flops_m) / (tv + tm) / 1e9,
                        "spmv_gflops": flops_v / tv / 1e9, "spmm_gflops": flops_m / tm / 1e9,
                        "spmv_ms": tv * 1e3, "spmm_ms": tm * 1e3}
-    spent = time.perf_counter() - c0
-    flush.close()
-    return {"value": runs["all"]["gflops"], "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"the headline matrix ({ro.nnz:,} nonzeros), SpMV + SpMM k={k}, FP64; 2 warm-up + "
-                      f"{reps} timed repetitions on {threads} threads and on 1 thread, each call after a "
-                      f"host LLC flush ({flush.bytes >> 20} MiB touched, 2x the {flush.llc >> 20} MiB of L3); "
-                      f"{spent:.1f} s in total",
-            "llc_flushed": True, "repetitions": reps, "warmup": 2,
-            "spmv_gflops": runs["all"]["spmv_gflops"], "spmm_gflops": runs["all"]["spmm_gflops"],
-            "one_thread": runs["one_thread"]}
+    return runs, time.perf_counter() - c0
 
 
 # ---------------------------------------------------------------- headline (c1)
