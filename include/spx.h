@@ -206,6 +206,15 @@ spx_status csr_plan_create_staged(int32_t m, int32_t n, int32_t nnz, const int32
 /* Rows per tile, tiles, tiles staged in LDS, and the largest window (X rows). */
 spx_status csr_plan_staged_info(const spx_plan *plan, int32_t *tile_rows, int32_t *ntiles, int32_t *nstaged,
                                 int32_t *max_cols);
+/* enable != 0: products through this staged plan run the pipelined kernel
+ * (persistent workgroups, two LDS tile buffers: tile t + 1's window, values
+ * and indices arrive through direct global-to-LDS loads while tile t is
+ * computed; the X reuse of Sec. 5 with the wait for each tile's loads
+ * overlapped) instead of one workgroup per tile; tiles that are not staged
+ * still gather directly, in a second launch.  Same results, bitwise.
+ * enable == 0 restores the default.  SPX_ERR_INVALID for a plan that is not
+ * staged. */
+spx_status csr_plan_staged_pipeline(spx_plan *plan, int32_t enable);
 
 /* ---------------------------------------------------------------- products
  * y <- A x.  vtype/xytype pairs: (F64, F64) plain FP64; (F32, F32) and

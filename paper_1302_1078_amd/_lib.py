@@ -95,6 +95,7 @@ SIGNATURES = {
     "csr_plan_staged_workspace_bytes": (ctypes.c_int, [i32, i32, i32, i32, ctypes.c_int, SZ]),
     "csr_plan_create_staged": (ctypes.c_int, [i32, i32, i32, P, P, i32, ctypes.c_int, P, ctypes.c_size_t, P, PP]),
     "csr_plan_staged_info": (ctypes.c_int, [P, P, P, P, P]),
+    "csr_plan_staged_pipeline": (ctypes.c_int, [P, i32]),
     "csr_plan_destroy": (None, [P]),
     "csr_spmv": (ctypes.c_int, [i32, i32, i32, P, P, P, ctypes.c_int, P, P, ctypes.c_int, P, P]),
     "csr_spmm": (ctypes.c_int, [i32, i32, i32, P, P, P, ctypes.c_int, i32, P, i64, P, i64,

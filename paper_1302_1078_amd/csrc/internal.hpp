@@ -138,7 +138,7 @@ struct spx_plan {
   double* partials;                   // device, [nseg * max_k]
   // X staging (csr_plan_create_staged; zero for a binned plan): rows in tiles
   // of tile_rows consecutive rows, each tile's distinct X rows staged in LDS
-  int32_t staged;                     // 1 for a staged plan
+  int32_t staged;                     // 1 for a staged plan, 2 for one run by the pipelined kernel
   int32_t k;                          // right-hand sides the windows were sized for
   int32_t xtype;                      // spx_dtype of X / Y
   int32_t kl, vec;                    // lane layout of the product (lanes per X row, elements per lane)

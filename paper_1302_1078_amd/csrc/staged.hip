@@ -289,7 +289,9 @@ __device__ __forceinline__ void accumulate_lds(const ProdArgs& a, const typename
 // One workgroup per tile of R = min(256 / KL, 64) rows, S = 256 / (R KL)
 // slots per row.  Dynamic LDS: the window (max_cols rows of k elements),
 // then the tile's values (as XT), window indices and row offsets.
-template <class C>
+// DIRECT_ONLY: serve only the tiles that are not staged (beside the
+// pipelined kernel, which serves the staged ones).
+template <class C, bool DIRECT_ONLY>
 __global__ __launch_bounds__(kWG) void k_staged(const ProdArgs a, const StageTiles st) {
   extern __shared__ __align__(16) unsigned char s_lds[];
   using XT = typename C::XT;
@@ -314,6 +316,7 @@ __global__ __launch_bounds__(kWG) void k_staged(const ProdArgs a, const StageTil
   const int32_t row = r0 + grp;
   const bool active = row < st.m;
   const bool nt = !(a.flags & SPX_FLAG_NO_NT_STORE);
+  if (DIRECT_ONLY && ucols >= 0) return;  // uniform
   if (ucols >= 0) {
     // ---- one round trip: window vectors, values, indices, row offsets
     const int32_t pb = __builtin_amdgcn_readfirstlane(a.rowptr[r0]);
@@ -397,22 +400,380 @@ __global__ __launch_bounds__(kWG) void k_staged(const ProdArgs a, const StageTil
   }
 }
 
+// ---------------------------------------------------------------- pipelined product
+// Persistent, double-buffered variant.  Each workgroup walks a sequence of
+// tiles (the tiles of one XCD taken in turn by its workgroups) with two LDS
+// tile buffers and five wavefronts.  In step t
+// the four compute wavefronts
+//   1. issue the loads of tile t + 1 into the other buffer -- window, values,
+//      window indices, row offsets -- as direct global-to-LDS loads
+//      (global_load_lds: no registers in between), and the column list of
+//      tile t + 2, which addresses the next step's window loads;
+//   2. compute tile t from LDS and leave its rows' results in an LDS output
+//      buffer;
+//   3. wait for their own loads and meet at the step's barrier.
+// The fifth wavefront writes the previous step's results from LDS to Y.
+// Why the split: a wavefront's vector-memory counter counts loads and stores
+// together and completes in order, so a wavefront that waits for a prefetch
+// would also wait for its own earlier stores.  The compute wavefronts issue
+// no global store and no global load besides the prefetch, so waiting for
+// their counter is waiting for the prefetch; the storing wavefront never
+// waits.  The barrier is a bare s_barrier behind lgkmcnt(0) (a release
+// fence would wait for every outstanding access).
+// LDS bytes per element: window 16-byte vectors as stored; values 8 (FP64)
+// or 4 (FP32; BF16 lands zero-extended in 4: 2-byte loads to LDS write one
+// dword per lane); window indices 4; row offsets 4; column list 4; results
+// as XT, R rows of k.
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+
+constexpr int kPipeThreads = kWG + kWave;  // four compute wavefronts and the storing one
+
+struct PipeLayout {
+  int32_t win, val, loc, rp, buf;  // byte offsets inside one tile buffer, and its size (whole rounds of loads)
+  int32_t cols, colbuf;            // the two column-list buffers: offset of the first, size of each
+  int32_t out, outbuf;             // the two result buffers: offset of the first, size of each
+  int32_t grid;                    // persistent workgroups
+};
+
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// This wavefront's global-to-LDS loads have landed, then the barrier.  Inline
+// asm, since the compiler's wait insertion may drop a builtin wait it does
+// not see a register reason for.
+__device__ __forceinline__ void loads_barrier() {
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// 4-byte words [0, words) of src into LDS dst, one word per thread and round
+// of the 256 compute threads; threads past `words` read src[0] into the
+// round's padding.
+__device__ __forceinline__ void dma_words(const uint32_t* src, int32_t words, unsigned char* dst, int tid) {
+  const int w = tid / kWave;
+  for (int32_t r = 0; r * kWG < words; ++r) {
+    const int32_t e = r * kWG + tid;
+    __builtin_amdgcn_global_load_lds((glb_void*)(src + (e < words ? e : 0)),
+                                     (lds_void*)(dst + (r * kWG + w * kWave) * 4), 4, 0, 0);
+  }
+}
+// The same for 2-byte elements (each lands zero-extended in a dword).
+__device__ __forceinline__ void dma_halves(const uint16_t* src, int32_t n, unsigned char* dst, int tid) {
+  const int w = tid / kWave;
+  for (int32_t r = 0; r * kWG < n; ++r) {
+    const int32_t e = r * kWG + tid;
+    __builtin_amdgcn_global_load_lds((glb_void*)(src + (e < n ? e : 0)),
+                                     (lds_void*)(dst + (r * kWG + w * kWave) * 4), 2, 0, 0);
+  }
+}
+
 template <class C>
+__device__ __forceinline__ typename C::XT lds_value(const unsigned char* val, int32_t e) {
+  using VT = typename C::VT;
+  if constexpr (sizeof(VT) == 8) return reinterpret_cast<const double*>(val)[e];
+  else if constexpr (sizeof(VT) == 4) return reinterpret_cast<const float*>(val)[e];
+  else return bf16_to_f32(static_cast<uint16_t>(reinterpret_cast<const uint32_t*>(val)[e]));
+}
+
+// A row's nonzeros q0..q1 (tile-relative) from the LDS buffer: as
+// accumulate_lds, with the values and window indices in their DMA layout.
+template <class C, int S>
+__device__ __forceinline__ void accumulate_pipe(const ProdArgs& a, const unsigned char* val, const uint32_t* loc,
+                                                const typename C::XT* xs, int32_t q0, int32_t q1, int slot, int col,
+                                                bool comp, typename C::AT (&acc)[C::VEC], Comp (&cacc)[C::VEC]) {
+  using XT = typename C::XT;
+  constexpr int VEC = C::VEC, U = C::U;
+  const bool colok = col < a.k;
+  const XT* Xb = xs + col;
+  for (int32_t q = q0 + slot; q < q1; q += U * S) {
+    bool h[U];
+    int32_t c[U];
+    XT v[U];
+#pragma unroll
+    for (int uu = 0; uu < U; ++uu) {
+      h[uu] = q + uu * S < q1;
+      c[uu] = h[uu] ? static_cast<int32_t>(loc[q + uu * S]) : 0;
+      v[uu] = h[uu] ? lds_value<C>(val, q + uu * S) : XT(0);
+    }
+    XT xv[U][VEC];
+#pragma unroll
+    for (int uu = 0; uu < U; ++uu) {
+      if (h[uu] && colok) {
+        load_x<XT, VEC>(Xb + c[uu] * a.k, xv[uu]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xv[uu][e] = XT(0);
+      }
+    }
+    if (!C::kComp || !comp) {
+#pragma unroll
+      for (int uu = 0; uu < U; ++uu)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (h[uu]) acc[e] = fma_t(v[uu], xv[uu][e], acc[e]);
+    } else if constexpr (C::kComp) {
+#pragma unroll
+      for (int uu = 0; uu < U; ++uu)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (h[uu]) cacc[e].add_prod(v[uu], xv[uu][e]);
+    }
+  }
+}
+
+// Tile record: window size (-1: not staged), column-list offset, first
+// nonzero and nonzero count.  All wave-uniform, read through the constant
+// address space (scalar loads, outside the vector-memory counter; the plan
+// arrays and rowptr are not written while a product runs).
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
+struct PipeTile {
+  int32_t ucols, off, pb, nz;
+};
+
+__device__ __forceinline__ PipeTile pipe_tile(const ProdArgs& a, const StageTiles& st, int32_t R, int32_t t,
+                                              bool valid) {
+  PipeTile pt{-1, 0, 0, 0};
+  if (!valid) return pt;
+  const int32_t r0 = t * R;
+  const int32_t r1 = min(r0 + R, st.m);
+  pt.ucols = ld_uniform(st.tile_cols + t);
+  pt.off = ld_uniform(st.tile_off + t);
+  pt.pb = ld_uniform(a.rowptr + r0);
+  pt.nz = ld_uniform(a.rowptr + r1) - pt.pb;
+  return pt;
+}
+
+// The group's final sums of one row (as finish_small, into LDS instead of Y).
+template <class C, int GG>
+__device__ __forceinline__ void finish_to_lds(bool comp, int slot, int col, int32_t k, typename C::AT (&acc)[C::VEC],
+                                              Comp (&cacc)[C::VEC], typename C::XT* orow) {
+  constexpr int KL = C::KL, VEC = C::VEC;
+  using XT = typename C::XT;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) acc[e] = group_sum<GG, KL>(acc[e]);
+  double dsum[VEC] = {};
+  if constexpr (C::kComp) {
+    if (__any(comp)) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) dsum[e] = group_sum<GG, KL>(comp ? cacc[e].value() : 0.0);
+    }
+  }
+  if (slot == 0 && col < k) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      if constexpr (C::kComp) orow[col + e] = comp ? static_cast<XT>(dsum[e]) : acc[e];
+      else orow[col + e] = acc[e];
+    }
+  }
+}
+
+template <class C>
+__global__ __launch_bounds__(kPipeThreads) void k_staged_pipe(const ProdArgs a, const StageTiles st,
+                                                              const PipeLayout L) {
+  extern __shared__ __align__(16) unsigned char s_lds[];
+  using XT = typename C::XT;
+  using AT = typename C::AT;
+  using VT = typename C::VT;
+  constexpr int KL = C::KL, VEC = C::VEC;
+  constexpr int R = tile_rows_for(KL);
+  constexpr int GG = kWG / R;   // lanes per row
+  constexpr int S = GG / KL;    // slots per row
+  static_assert(VEC > 1 && S >= 1 && GG * R == kWG, "staged layout");
+  const int tid = threadIdx.x;
+  // Tile order: XCD j (workgroups g = j mod 8, all resident at once) walks
+  // the contiguous eighth j of the tiles, its workgroups taking consecutive
+  // tiles in turn, so the tiles in flight on one XCD are neighbours and the
+  // X rows they share stay in that XCD's L2.  Step i of this workgroup is
+  // tile base + i * stride, for i < nsteps.
+  const int g = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x));
+  const int32_t H = L.grid / 8, j = g % 8, h = g / 8;
+  const int32_t lo = static_cast<int32_t>((static_cast<int64_t>(st.ntiles) * j) / 8);
+  const int32_t hi = static_cast<int32_t>((static_cast<int64_t>(st.ntiles) * (j + 1)) / 8);
+  const int32_t base = __builtin_amdgcn_readfirstlane(lo + h), stride = H;
+  const int32_t nsteps = __builtin_amdgcn_readfirstlane(base < hi ? (hi - base + H - 1) / H : 0);
+  if (nsteps <= 0) return;
+  auto tile_at = [&](int32_t i) { return base + i * stride; };
+  // (LDS pointers are formed from s_lds by arithmetic only, so that the
+  // compiler keeps them in the LDS address space)
+  auto colbuf = [&](int cb) { return s_lds + L.cols + cb * L.colbuf; };
+  auto tilebuf = [&](int b) { return s_lds + b * L.buf; };
+  auto outbuf = [&](int b) { return reinterpret_cast<XT*>(s_lds + L.out + b * L.outbuf); };
+
+  if (tid >= kWG) {
+    // ---- the storing wavefront: during step t it writes the results of
+    // tile t - 1, and after the last step those of the last tile.  It meets
+    // the compute wavefronts at every barrier (two in the prologue, one per
+    // step).
+    const int lane = tid - kWG;
+    const bool nt = !(a.flags & SPX_FLAG_NO_NT_STORE);
+    auto store_tile = [&](int32_t ip) {
+      const int32_t tp = tile_at(ip);
+      if (ld_uniform(st.tile_cols + tp) < 0) return;  // served by k_staged
+      const XT* o = outbuf(ip & 1);
+      const int32_t rows = min(R, st.m - tp * R);
+      XT* Y = static_cast<XT*>(a.Y) + static_cast<int64_t>(tp) * R * a.ldy;
+      for (int32_t i = lane; i < rows * a.k; i += kWave) {
+        const int32_t r = i / a.k, c = i - r * a.k;
+        const XT v = o[i];
+        if (nt) __builtin_nontemporal_store(v, Y + static_cast<int64_t>(r) * a.ldy + c);
+        else Y[static_cast<int64_t>(r) * a.ldy + c] = v;
+      }
+    };
+    lds_barrier();
+    lds_barrier();
+    for (int32_t i = 0; i < nsteps; ++i) {
+      if (i > 0) store_tile(i - 1);
+      lds_barrier();
+    }
+    store_tile(nsteps - 1);
+    return;
+  }
+
+  // ---- the compute wavefronts
+  const int lpr = a.k / VEC;  // 16-byte vectors per X row
+  const XT* X = static_cast<const XT*>(a.X);
+  const VT* values = static_cast<const VT*>(a.values);
+  const int w = tid / kWave;
+  auto issue_cols = [&](const PipeTile& pt, int cb) {
+    if (pt.ucols > 0) dma_words(reinterpret_cast<const uint32_t*>(st.tcols + pt.off), pt.ucols, colbuf(cb), tid);
+  };
+  // window (addressed by the column list in column buffer cb), values,
+  // window indices and row offsets of a staged tile into tile buffer b
+  auto issue_tile = [&](const PipeTile& pt, int32_t t, int cb, int b) {
+    unsigned char* buf = tilebuf(b);
+    const int32_t* cl = reinterpret_cast<const int32_t*>(colbuf(cb));
+    const int32_t nvec = pt.ucols * lpr;
+    for (int32_t q = 0; q * kWG < nvec; ++q) {
+      const int32_t i = q * kWG + tid;
+      const int32_t j = i < nvec ? i / lpr : 0;
+      const int32_t c = i < nvec ? (i - j * lpr) * VEC : 0;
+      __builtin_amdgcn_global_load_lds((glb_void*)(X + static_cast<int64_t>(cl[j]) * a.ldx + c),
+                                       (lds_void*)(buf + L.win + (q * kWG + w * kWave) * 16), 16, 0, 0);
+    }
+    if constexpr (sizeof(VT) == 2)
+      dma_halves(reinterpret_cast<const uint16_t*>(values + pt.pb), pt.nz, buf + L.val, tid);
+    else
+      dma_words(reinterpret_cast<const uint32_t*>(values + pt.pb), pt.nz * static_cast<int32_t>(sizeof(VT) / 4),
+                buf + L.val, tid);
+    dma_halves(st.loc + pt.pb, pt.nz, buf + L.loc, tid);
+    dma_words(reinterpret_cast<const uint32_t*>(a.rowptr + t * R), min(R + 1, st.m - t * R + 1), buf + L.rp, tid);
+  };
+  const int grp = tid / GG, ln = tid % GG, slot = ln / KL, kl = ln % KL;
+  PipeTile cur = pipe_tile(a, st, R, tile_at(0), true);
+  PipeTile nxt = pipe_tile(a, st, R, tile_at(1), nsteps > 1);
+  // prologue: step 0's column list, then its data and step 1's column list
+  issue_cols(cur, 0);
+  loads_barrier();
+  if (cur.ucols >= 0) issue_tile(cur, tile_at(0), 0, 0);
+  issue_cols(nxt, 1);
+  loads_barrier();
+  for (int32_t i = 0; i < nsteps; ++i) {
+    const int b = i & 1;
+    const int32_t t = tile_at(i);
+    const PipeTile nn = pipe_tile(a, st, R, tile_at(i + 2), i + 2 < nsteps);
+    // 1. prefetch: step i + 1's tile (column list in column buffer b ^ 1),
+    //    and the column list of step i + 2 into column buffer b
+    if (nxt.ucols >= 0) issue_tile(nxt, tile_at(i + 1), b ^ 1, b ^ 1);
+    issue_cols(nn, b);
+    // 2. tile t from buffer b into result buffer b
+    if (cur.ucols >= 0) {
+      const unsigned char* buf = tilebuf(b);
+      const XT* xs = reinterpret_cast<const XT*>(buf + L.win);
+      const unsigned char* val = buf + L.val;
+      const uint32_t* loc = reinterpret_cast<const uint32_t*>(buf + L.loc);
+      const int32_t* srp = reinterpret_cast<const int32_t*>(buf + L.rp);
+      const bool active = t * R + grp < st.m;
+      const int32_t q0 = active ? srp[grp] - cur.pb : 0, q1 = active ? srp[grp + 1] - cur.pb : 0;
+      const bool comp = C::kComp && (q1 - q0 > a.kahan_len);
+      XT* orow = outbuf(b) + grp * a.k;
+      for (int c0 = 0; c0 < a.k; c0 += KL * VEC) {
+        const int col = c0 + kl * VEC;
+        AT acc[VEC];
+        Comp cacc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          acc[e] = AT(0);
+          cacc[e].init();
+        }
+        accumulate_pipe<C, S>(a, val, loc, xs, q0, q1, slot, col, comp, acc, cacc);
+        finish_to_lds<C, GG>(comp, slot, col, a.k, acc, cacc, orow);
+      }
+    }
+    // 3. the prefetch has landed (this wavefront's counter holds nothing else)
+    loads_barrier();
+    cur = nxt;
+    nxt = nn;
+  }
+}
+
+template <class C, bool DIRECT_ONLY>
 spx_status launch_kc(const ProdArgs& a, const StageTiles& s, size_t lds, hipStream_t st) {
   const int64_t grid = (static_cast<int64_t>(s.ntiles) + 7) / 8 * 8;
   if (grid > 0x7fffffff) return fail(SPX_ERR_UNSUPPORTED, "staged product: grid too large");
+  if (DIRECT_ONLY) lds = 0;
   if (lds > 0)
-    SPX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_staged<C>),
+    SPX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_staged<C, DIRECT_ONLY>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  k_staged<C><<<static_cast<unsigned>(grid), kWG, lds, st>>>(a, s);
+  k_staged<C, DIRECT_ONLY><<<static_cast<unsigned>(grid), kWG, lds, st>>>(a, s);
   SPX_LAUNCHED("k_staged");
   return SPX_OK;
 }
 
+// LDS buffers of the pipelined kernel, sized to the plan's largest staged
+// tile, and a persistent grid of as many workgroups as fit on the device.
+template <class C>
+spx_status launch_pipe(const ProdArgs& a, const StageTiles& s, int32_t tile_rows, hipStream_t st) {
+  const int64_t xb = sizeof(typename C::XT);
+  const int64_t vb = sizeof(typename C::VT) == 8 ? 8 : 4;
+  // every region holds whole rounds of loads (lanes past the end write padding)
+  auto rounds = [](int64_t elems, int64_t bytes_per_lane) {
+    return ((elems + kWG - 1) / kWG) * kWG * bytes_per_lane;
+  };
+  PipeLayout L;
+  L.win = 0;
+  L.val = static_cast<int32_t>(rounds(static_cast<int64_t>(s.max_cols) * (a.k * xb / 16), 16));
+  L.loc = L.val + static_cast<int32_t>(rounds(static_cast<int64_t>(s.max_nnz) * (vb / 4), 4));
+  L.rp = L.loc + static_cast<int32_t>(rounds(s.max_nnz, 4));
+  L.buf = L.rp + static_cast<int32_t>(rounds(tile_rows + 1, 4));
+  L.cols = 2 * L.buf;
+  L.colbuf = static_cast<int32_t>(rounds(s.max_cols, 4));
+  L.out = L.cols + 2 * L.colbuf;
+  L.outbuf = static_cast<int32_t>((static_cast<int64_t>(tile_rows) * a.k * xb + 15) & ~int64_t(15));
+  const size_t lds = static_cast<size_t>(L.out) + 2 * static_cast<size_t>(L.outbuf);
+  const void* fn = reinterpret_cast<const void*>(&k_staged_pipe<C>);
+  SPX_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  int dev = 0, cus = 0, per_cu = 0;
+  SPX_HIP(hipGetDevice(&dev));
+  SPX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPipeThreads, lds));
+  if (per_cu < 1) return fail(SPX_ERR_UNSUPPORTED, "staged product: %zu B of LDS per workgroup do not fit", lds);
+  // all workgroups resident at once, a multiple of the 8 XCDs (8 at least)
+  L.grid = static_cast<int32_t>(std::max<int64_t>(8, (static_cast<int64_t>(cus) * per_cu) / 8 * 8));
+  k_staged_pipe<C><<<static_cast<unsigned>(L.grid), kPipeThreads, lds, st>>>(a, s, L);
+  SPX_LAUNCHED("k_staged_pipe");
+  return SPX_OK;
+}
+
+template <class C>
+spx_status launch_staged_kernel(const ProdArgs& a, const StageTiles& s, size_t lds, int32_t tile_rows,
+                                int32_t nstaged, bool pipelined, hipStream_t st) {
+  if (!pipelined) return launch_kc<C, false>(a, s, lds, st);
+  if (nstaged > 0) {
+    const spx_status r = launch_pipe<C>(a, s, tile_rows, st);
+    if (r != SPX_OK) return r;
+  }
+  if (nstaged < s.ntiles) return launch_kc<C, true>(a, s, lds, st);
+  return SPX_OK;
+}
+
 template <typename VT, typename XT, int VECMAX>
-spx_status launch_vt_staged(const ProdArgs& a, const StageTiles& s, size_t lds, int kl, int vec, hipStream_t st) {
-#define SPX_CASE(KL_, VEC_) \
-  if (kl == KL_ && vec == VEC_) return launch_kc<Cfg<VT, XT, KL_, VEC_>>(a, s, lds, st);
+spx_status launch_vt_staged(const ProdArgs& a, const StageTiles& s, size_t lds, int32_t tile_rows, int32_t nstaged,
+                            bool pipelined, int kl, int vec, hipStream_t st) {
+#define SPX_CASE(KL_, VEC_)                                                                      \
+  if (kl == KL_ && vec == VEC_)                                                                  \
+    return launch_staged_kernel<Cfg<VT, XT, KL_, VEC_>>(a, s, lds, tile_rows, nstaged, pipelined, st);
   SPX_CASE(1, VECMAX) SPX_CASE(2, VECMAX) SPX_CASE(4, VECMAX) SPX_CASE(8, VECMAX)
   SPX_CASE(16, VECMAX) SPX_CASE(32, VECMAX)
 #undef SPX_CASE
@@ -435,9 +796,12 @@ spx_status launch_staged(ProdArgs& a, const spx_plan* p, int32_t m, int vt, int 
   const size_t lds = (static_cast<size_t>(p->max_cols) * p->k + p->max_nnz) * xb +
                      static_cast<size_t>((p->max_nnz + 1) & ~1) * 2 + static_cast<size_t>(p->tile_rows + 1) * 4;
   if (p->ntiles == 0) return SPX_OK;
-  if (vt == SPX_F64 && xt == SPX_F64) return launch_vt_staged<double, double, 2>(a, s, lds, kl, vec, st);
-  if (vt == SPX_F32 && xt == SPX_F32) return launch_vt_staged<float, float, 4>(a, s, lds, kl, vec, st);
-  if (vt == SPX_BF16 && xt == SPX_F32) return launch_vt_staged<uint16_t, float, 4>(a, s, lds, kl, vec, st);
+  const int32_t R = p->tile_rows, ns = p->nstaged;
+  const bool pl = p->staged == 2;
+  if (vt == SPX_F64 && xt == SPX_F64) return launch_vt_staged<double, double, 2>(a, s, lds, R, ns, pl, kl, vec, st);
+  if (vt == SPX_F32 && xt == SPX_F32) return launch_vt_staged<float, float, 4>(a, s, lds, R, ns, pl, kl, vec, st);
+  if (vt == SPX_BF16 && xt == SPX_F32)
+    return launch_vt_staged<uint16_t, float, 4>(a, s, lds, R, ns, pl, kl, vec, st);
   return fail(SPX_ERR_UNSUPPORTED, "staged product: dtype pair (%d, %d)", vt, xt);
 }
 
@@ -520,6 +884,13 @@ extern "C" spx_status csr_plan_create_staged(int32_t m, int32_t n, int32_t nnz, 
   p->tcols = w.tcols;
   p->loc = w.loc;
   *out = p;
+  return SPX_OK;
+}
+
+extern "C" spx_status csr_plan_staged_pipeline(spx_plan* p, int32_t enable) {
+  if (!p) return fail(SPX_ERR_INVALID, "csr_plan_staged_pipeline: plan is null");
+  if (!p->staged) return fail(SPX_ERR_INVALID, "csr_plan_staged_pipeline: not a staged plan");
+  p->staged = enable ? 2 : 1;
   return SPX_OK;
 }
 

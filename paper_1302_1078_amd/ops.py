@@ -182,9 +182,11 @@ class Plan:
         return cls(A.rowptr, A.m, A.n, A.nnz, opts if opts is not None else default_opts(k, A.values.dtype))
 
     @classmethod
-    def staged(cls, A: CSR, k: int, xdtype=torch.float64) -> "Plan":
+    def staged(cls, A: CSR, k: int, xdtype=torch.float64, pipelined: bool = False) -> "Plan":
         """Staged plan (csr_plan_create_staged): tiles of consecutive rows whose
-        X windows are copied into LDS, for SpMM with exactly this k and X type."""
+        X windows are copied into LDS, for SpMM with exactly this k and X type.
+        pipelined: run the persistent double-buffered kernel
+        (csr_plan_staged_pipeline)."""
         L = _lib.load()
         _dev(A.rowptr, A.colind)
         xt = _lib.SPX_F64 if xdtype == torch.float64 else _lib.SPX_F32
@@ -200,6 +202,8 @@ class Plan:
                                        _ptr(self.workspace), nb.value, _stream(), ctypes.byref(h)),
               "csr_plan_create_staged")
         self.handle = h
+        if pipelined:
+            check(L.csr_plan_staged_pipeline(h, 1), "csr_plan_staged_pipeline")
         return self
 
     def staged_info(self) -> dict:

@@ -178,3 +178,68 @@ def test_staged_empty_and_tiny(spx, torch):
         plan = spx.Plan.staged(G, 8)
         y = spx.spmm(G, dev(torch, np.ascontiguousarray(X)), plan=plan).cpu().numpy()
         assert np.array_equal(y, oracle.spmm(A, X)) if m else y.size == 0
+
+
+# ---------------------------------------------------------------- pipelined kernel
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("k", [2, 8, 16, 100])
+def test_pipelined_equals_one_round_f64(spx, torch, kind, k):
+    """The persistent double-buffered kernel does each row's arithmetic in the
+    same order as the one-workgroup-per-tile kernel: bitwise the same Y, and
+    within the FP64 bars of the oracle."""
+    A = matrix(kind, seed=11)
+    G = to_gpu(A)
+    X = spgen.uniform(A.n * k, 12).reshape(A.n, k)
+    Xd = dev(torch, X)
+    y1 = spx.spmm(G, Xd, plan=spx.Plan.staged(G, k))
+    y2 = spx.spmm(G, Xd, plan=spx.Plan.staged(G, k, pipelined=True))
+    assert torch.equal(y1.view(torch.int64), y2.view(torch.int64)), (kind, k)
+    check_f64(y2.cpu().numpy(), A, X, (kind, k, "pipelined"))
+
+
+@pytest.mark.parametrize("vname", ["f32", "bf16"])
+@pytest.mark.parametrize("kind", ["stencil27", "powerlaw", "one_long_row", "empty_rows"])
+@pytest.mark.parametrize("k", [4, 16, 32])
+def test_pipelined_equals_one_round_precision(spx, torch, vname, kind, k):
+    A = matrix(kind, seed=13)
+    G, _ = quantised(A, vname, torch)
+    Xq = dev(torch, spgen.to_f32(spgen.uniform(A.n * k, 14).reshape(A.n, k)))
+    y1 = spx.spmm(G, Xq, plan=spx.Plan.staged(G, k, torch.float32))
+    y2 = spx.spmm(G, Xq, plan=spx.Plan.staged(G, k, torch.float32, pipelined=True))
+    assert torch.equal(y1.view(torch.int32), y2.view(torch.int32)), (vname, kind, k)
+
+
+def test_pipelined_graph_and_edges(spx, torch):
+    A = matrix("stencil27", seed=15)
+    G = to_gpu(A)
+    k = 16
+    X = dev(torch, spgen.uniform(A.n * k, 16).reshape(A.n, k))
+    plan = spx.Plan.staged(G, k, pipelined=True)
+    Y = torch.empty((A.m, k), dtype=torch.float64, device="cuda:0")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        spx.spmm(G, X, Y=Y, plan=plan)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        spx.spmm(G, X, Y=Y, plan=plan)
+    for r in range(3):
+        X.mul_(-1.0)
+        ref = spx.spmm(G, X, plan=spx.Plan.staged(G, k))  # one-round kernel, eager, between replays
+        Y.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Y.view(torch.int64), ref.view(torch.int64)), r
+    # empty and tiny matrices, a single tile, and a plan that is not staged
+    for m, n, r_, c_ in [(0, 5, [], []), (1, 1, [0], [0]), (300, 7, [299], [6])]:
+        B = oracle.csr_from_coo(m, n, np.array(r_, np.int32), np.array(c_, np.int32), np.ones(len(r_)))
+        H = to_gpu(B)
+        Xs = spgen.uniform(max(n, 1) * 8, 1).reshape(max(n, 1), 8)[:n]
+        y = spx.spmm(H, dev(torch, np.ascontiguousarray(Xs)), plan=spx.Plan.staged(H, 8, pipelined=True)).cpu().numpy()
+        assert np.array_equal(y, oracle.spmm(B, Xs)) if m else y.size == 0
+    from paper_1302_1078_amd import _lib
+    binned = spx.Plan.for_matrix(G, spx.default_opts(k))
+    assert _lib.load().csr_plan_staged_pipeline(binned.handle, 1) == _lib.SPX_ERR_INVALID
