@@ -275,13 +275,18 @@ def bench_c2(ctx, A1=None):
                      "frac_hbm": b / t / 1e9 / PEAK_HBM_GBS, "bytes": b}
                 if k > 1 and name.startswith("stencil"):
                     # the staged plan (row tiles' X windows in LDS), an opt-in
-                    # alternative for banded matrices, on the same data
+                    # alternative for banded matrices, on the same data, and its
+                    # persistent double-buffered form
                     ps = spx.Plan.staged(Aq, k, Xd.dtype)
+                    pp = spx.Plan.staged(Aq, k, Xd.dtype, pipelined=True)
                     ys = torch.empty_like(yd)
-                    ts = float(ctx["timer"].run([lambda: spx.spmm(Aq, Xd, Y=ys, plan=ps)], ctx["fsteps"], 3)[:, 0].mean())
+                    ts, tp = ctx["timer"].run([lambda: spx.spmm(Aq, Xd, Y=ys, plan=ps),
+                                               lambda: spx.spmm(Aq, Xd, Y=ys, plan=pp)], ctx["fsteps"], 3).mean(axis=0)
+                    ts, tp = float(ts), float(tp)
                     r["staged_plan"] = {"us": ts * 1e6, "eff_gbs": b / ts / 1e9, "frac_hbm": b / ts / 1e9 / PEAK_HBM_GBS,
-                                        "speedup_vs_default_plan": t / ts, **ps.staged_info()}
-                    del ps, ys
+                                        "speedup_vs_default_plan": t / ts, **ps.staged_info(),
+                                        "pipelined_us": tp * 1e6, "pipelined_speedup_vs_default_plan": t / tp}
+                    del ps, pp, ys
                 if vname != "f64":
                     r["rel2_vs_gpu_fp64"] = max(rel2(yh[:, j], y3[:, j]) for j in range(k))
                     y5 = fp64_product(A.with_values(vals.double()), Xq64, k)
