@@ -407,3 +407,37 @@ def test_autograd_saved_gather_bitwise(spx, torch, dtype):
         grads.append((y.detach(), v.grad, xt.grad))
     for a, b in zip(*grads):
         assert torch.equal(a.view(torch.int8), b.view(torch.int8))
+
+
+def test_saved_gather_graph_replay(spx, torch):
+    """The saved-gather forward and its sampled dot captured in a HIP graph:
+    every replay (x and dy changed eagerly in between) equals eager calls."""
+    A = matrix("powerlaw", seed=47)
+    G = to_gpu(A)
+    plan = spx.Plan.for_matrix(G, spx.default_opts(1))
+    x = dev(torch, spgen.uniform(A.n, 48))
+    dy = dev(torch, spgen.normal(A.m, 49))
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda:0")
+    xg = torch.empty(A.nnz, dtype=torch.float64, device="cuda:0")
+    out = torch.empty(A.nnz, dtype=torch.float64, device="cuda:0")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on a side stream before capture
+        spx.spmv_save(G, x, y=y, xsave=xg, plan=plan)
+        spx.sddmm_saved(G, dy, xg, plan=plan, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        spx.spmv_save(G, x, y=y, xsave=xg, plan=plan)
+        spx.sddmm_saved(G, dy, xg, plan=plan, out=out)
+    for r in range(3):
+        x.mul_(-0.5)
+        dy.add_(1.0)
+        y_ref = spx.spmv(G, x, plan=plan)
+        out_ref = spx.sddmm(G, dy, x, plan=plan)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y.view(torch.int64), y_ref.view(torch.int64)), r
+        assert torch.equal(out.view(torch.int64), out_ref.view(torch.int64)), r
