@@ -822,6 +822,16 @@ def main():
               "setup_s": round(setup_s, 2), "wall_s_timed_incl_flush": round(wall, 4),
               "source_hash": source_hash()}
 
+    # the same SpMV through a plan with hot x attached (the 65,536 most-used
+    # columns' x entries packed together; opt-in, not the headline plan)
+    plan_h = spx.Plan.for_matrix(A, spx.default_opts(1)).attach_hot_x(A, 65536)
+    yh = torch.empty_like(y)
+    th = timer.run([lambda: spx.spmv(A, x, y=yh, plan=plan_h)], args.steps, 2)[:, 0]
+    detail["spmv_hot_x"] = dict(stats(th, flops_v, bytes_v, float("nan")), hot_columns=65536,
+                                speedup_vs_default_plan=float(tv.mean() / th.mean()),
+                                equals_default_bitwise=bool(torch.equal(yh.view(torch.int64), y.view(torch.int64))))
+    del plan_h, yh
+
     # random-access ceilings of the two gathers, on buffers the size of X and x
     gather = {}
     for kind, nbytes, per_round, label in (("gather_rows", n * k * 8, 8, "X_rows_128B"),

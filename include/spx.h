@@ -216,6 +216,25 @@ spx_status csr_plan_staged_info(const spx_plan *plan, int32_t *tile_rows, int32_
  * staged. */
 spx_status csr_plan_staged_pipeline(spx_plan *plan, int32_t enable);
 
+/* Hot x for SpMV (the x reuse of Sec. 4.1-4.2): ranks the pattern's columns
+ * by use (as csr_degree_order) and keeps the `hot` most used, 1 <= hot <=
+ * 2^20.  Every later csr_spmv through the plan (k = 1, x of type xtype: F64
+ * or F32) first copies those hot x entries into a compact plan buffer (one
+ * small kernel) and reads them from there, many to a cache line, instead of
+ * one line of x each.
+ * Results are bitwise those of the plan without hot x.  colind are the
+ * pattern's column indices (the plan's n and nnz); the workspace
+ * (csr_plan_hot_x_workspace_bytes) holds the plan's copy of them with hot
+ * columns marked, the hot list and the x buffer, and must outlive the plan.
+ * SpMM, the transpose and the sampled dot ignore the hot x.  Calls through
+ * one plan with hot x share its x buffer: calls that may overlap (several
+ * streams) race, as they do on a plan's split-row partials.  A staged plan
+ * is rejected (SPX_ERR_UNSUPPORTED); an x of another type at call time is
+ * SPX_ERR_INVALID. */
+spx_status csr_plan_hot_x_workspace_bytes(int32_t n, int32_t nnz, int32_t hot, size_t *bytes);
+spx_status csr_plan_attach_hot_x(spx_plan *plan, int32_t n, int32_t nnz, const int32_t *colind, int32_t hot,
+                                 spx_dtype xtype, void *workspace, size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------- products
  * y <- A x.  vtype/xytype pairs: (F64, F64) plain FP64; (F32, F32) and
  * (BF16, F32) reduced-precision values with FP32 vectors.  x has n entries,

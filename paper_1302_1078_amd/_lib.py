@@ -96,6 +96,8 @@ SIGNATURES = {
     "csr_plan_create_staged": (ctypes.c_int, [i32, i32, i32, P, P, i32, ctypes.c_int, P, ctypes.c_size_t, P, PP]),
     "csr_plan_staged_info": (ctypes.c_int, [P, P, P, P, P]),
     "csr_plan_staged_pipeline": (ctypes.c_int, [P, i32]),
+    "csr_plan_hot_x_workspace_bytes": (ctypes.c_int, [i32, i32, i32, SZ]),
+    "csr_plan_attach_hot_x": (ctypes.c_int, [P, i32, i32, P, i32, ctypes.c_int, P, ctypes.c_size_t, P]),
     "csr_plan_destroy": (None, [P]),
     "csr_spmv": (ctypes.c_int, [i32, i32, i32, P, P, P, ctypes.c_int, P, P, ctypes.c_int, P, P]),
     "csr_spmm": (ctypes.c_int, [i32, i32, i32, P, P, P, ctypes.c_int, i32, P, i64, P, i64,

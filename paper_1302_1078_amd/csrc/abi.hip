@@ -109,6 +109,17 @@ spx_status product(const char* who, int32_t m, int32_t n, int32_t nnz, const int
     a.xsave = xsave;
     return launch_product_save(a, vt, xt, as_stream(stream));
   }
+  if (plan && plan->hot > 0 && k == 1 && !vperm && nnz > 0) {
+    if (xt != plan->hot_xtype)
+      return fail(SPX_ERR_INVALID, "%s: the plan's hot x was attached for x type %d, called with %d", who,
+                  plan->hot_xtype, xt);
+    a.colind = plan->colind_hot;
+    a.X2 = plan->x_hot;
+    a.ldx2 = plan->hot;
+    const spx_status sh = gather_hot_x(plan, X, as_stream(stream));
+    if (sh != SPX_OK) return sh;
+    return launch_product_hot(a, vt, xt, as_stream(stream));
+  }
   return launch_product(a, vt, xt, kl, vec, as_stream(stream));
 }
 

@@ -151,12 +151,24 @@ struct spx_plan {
   int32_t* tile_off;                  // device, [ntiles + 1]: offset of the tile's column list
   int32_t* tcols;                     // device: the tiles' sorted distinct columns, concatenated
   uint16_t* loc;                      // device, [nnz]: window index of each nonzero of a staged tile
+  // hot x (csr_plan_attach_hot_x; hot == 0: none): SpMV keeps the x entries
+  // of the hot most-used columns in LDS
+  int32_t hot;                        // number of hot columns
+  int32_t hot_xtype;                  // spx_dtype of the x it serves
+  const int32_t* hot_cols;            // device, [hot]: the hot columns, most used first
+  const int32_t* colind_hot;          // device, [nnz]: colind with hot columns as ~slot
+  void* x_hot;                        // device, [hot] of hot_xtype: x of the hot columns, per call
 };
 
 namespace spx {
 // Launch one fused product over a prepared bin table (product.hip).
 spx_status launch_product(ProdArgs& a, int vt, int xt, int kl, int vec, hipStream_t st);
 spx_status launch_product_save(ProdArgs& a, int vt, int xt, hipStream_t st);
+// SpMV through a plan with hot x (a.colind = the plan's colind_hot, a.X2 = its
+// x_hot, already filled, a.ldx2 = hot).
+spx_status launch_product_hot(ProdArgs& a, int vt, int xt, hipStream_t st);
+// Fill plan->x_hot from x (hot.hip).
+spx_status gather_hot_x(const spx_plan* plan, const void* x, hipStream_t st);
 // Fill a ProdArgs bin table from a plan, or from the unbinned heuristic.
 // `own_launch`: the table drives a launch of its own (not a tile list shared
 // with other matrices), so a stream bin too small to fill the device is

@@ -145,7 +145,29 @@ spx_status launch_save(ProdArgs& a, unsigned grid, hipStream_t st) {
   return launch_k<Cfg<VT, XT, 1, 1, true>, false>(a, grid, st);
 }
 
+// SpMV with hot x (a.X2: the compact hot entries).
+template <typename VT, typename XT>
+spx_status launch_hot(ProdArgs& a, unsigned grid, hipStream_t st) {
+  bool mr = false;
+  for (int i = 0; i < a.nbins; ++i) mr = mr || (a.bins[i].rpg > 1);
+  if (mr) return launch_k<Cfg<VT, XT, 1, 1, false, true>, true>(a, grid, st);
+  return launch_k<Cfg<VT, XT, 1, 1, false, true>, false>(a, grid, st);
+}
+
 }  // namespace
+
+spx_status launch_product_hot(ProdArgs& a, int vt, int xt, hipStream_t st) {
+  if (a.k != 1 || !a.X2 || a.ldx2 <= 0) return fail(SPX_ERR_INVALID, "hot x: k must be 1 with hot entries set");
+  int64_t grid = 0;
+  for (int i = 0; i < a.nbins; ++i) grid = a.bins[i].blk_begin + a.bins[i].nblk;
+  if (grid == 0) return SPX_OK;
+  if (grid > 0x7fffffff) return fail(SPX_ERR_UNSUPPORTED, "grid too large");
+  const unsigned g = static_cast<unsigned>(grid);
+  if (vt == SPX_F64 && xt == SPX_F64) return launch_hot<double, double>(a, g, st);
+  if (vt == SPX_F32 && xt == SPX_F32) return launch_hot<float, float>(a, g, st);
+  if (vt == SPX_BF16 && xt == SPX_F32) return launch_hot<uint16_t, float>(a, g, st);
+  return fail(SPX_ERR_UNSUPPORTED, "unsupported value/vector dtype pair (%d, %d)", vt, xt);
+}
 
 spx_status launch_product_save(ProdArgs& a, int vt, int xt, hipStream_t st) {
   if (a.k != 1 || !a.xsave) return fail(SPX_ERR_INVALID, "saved gather: k must be 1 and xsave set");

@@ -24,7 +24,12 @@ constexpr int kUnroll = SPX_UNROLL;
 // SAVE_: SpMV that also stores every gathered x[colind[p]] at xsave[p], so
 // that the gradient with respect to the values (out[p] = dy[row(p)] x[colind[p]])
 // can stream the operand instead of gathering it again.
-template <typename VT_, typename XT_, int KL_, int VEC_, bool SAVE_ = false>
+// HOT_: SpMV through a plan with hot x attached: the column indices are the
+// plan's copy, in which the H most-used columns appear as ~slot (negative);
+// their x entries are read from the compact copy x_hot (ProdArgs::X2, filled
+// per call), where 16 (FP64) or 32 (FP32) of them share a 128-byte line
+// instead of one per line of x.
+template <typename VT_, typename XT_, int KL_, int VEC_, bool SAVE_ = false, bool HOT_ = false>
 struct Cfg {
   using VT = VT_;  // stored value type: double, float or uint16_t (bf16 bits)
   using XT = XT_;  // vector / dense type: double or float
@@ -37,7 +42,9 @@ struct Cfg {
   static constexpr bool kNT = (KL_ * VEC_ == 1);
   static constexpr int U = (KL_ * VEC_ == 1) ? kUnroll : SPX_UNROLL_MM;
   static constexpr bool kSave = SAVE_;
+  static constexpr bool kHot = HOT_;
   static_assert(!SAVE_ || KL_ * VEC_ == 1, "the saved gather is an SpMV (k = 1) feature");
+  static_assert(!HOT_ || (KL_ * VEC_ == 1 && !SAVE_), "hot x is a plain SpMV (k = 1) feature");
   // look-ahead past a row's end is at most U x 256 slots (SPX_MAX_NNZ headroom)
   static_assert(U >= 1 && U * kWG <= 4096, "unroll depth");
 };
@@ -78,6 +85,17 @@ __device__ __forceinline__ typename C::XT value_at(const ProdArgs& a, int32_t p)
   const int32_t q = a.vperm ? ld_mat<C::kNT>(a.vperm + p) : p;
   return static_cast<typename C::XT>(
       ValueLoad<typename C::VT>::template get<C::kNT>(static_cast<const typename C::VT*>(a.values) + q));
+}
+
+// x entry of column index c (SpMV): from the compact hot copy when c is a
+// hot slot (~slot < 0, HOT variant), else from x.
+template <class C>
+__device__ __forceinline__ typename C::XT x_at(const ProdArgs& a, const typename C::XT* X, int32_t c, int64_t ldx) {
+  if constexpr (C::kHot) {
+    const typename C::XT* xh = static_cast<const typename C::XT*>(a.X2);
+    return c < 0 ? xh[~c] : X[static_cast<int64_t>(c) * ldx];
+  }
+  return X[static_cast<int64_t>(c) * ldx];
 }
 
 // The gathered x[colind[p]] of nonzero p, kept for the backward (save variant).
@@ -146,7 +164,8 @@ __device__ __forceinline__ void accumulate(const ProdArgs& a, int32_t p0, int32_
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (h[u] && colok) {
-        load_x<XT, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
+        if constexpr (C::kHot) xv[u][0] = x_at<C>(a, X, c[u], ldx);
+        else load_x<XT, VEC>(X + static_cast<int64_t>(c[u]) * ldx, xv[u]);
       } else {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) xv[u][e] = XT(0);
@@ -271,7 +290,8 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         if (has[j]) {
-          load_x<XT, VEC>(X + static_cast<int64_t>(c[j]) * a.ldx, xv[j]);
+          if constexpr (C::kHot) xv[j][0] = x_at<C>(a, X, c[j], a.ldx);
+          else load_x<XT, VEC>(X + static_cast<int64_t>(c[j]) * a.ldx, xv[j]);
         } else {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) xv[j][e] = XT(0);
@@ -303,7 +323,8 @@ __device__ __forceinline__ void do_rows(const ProdArgs& a, const BinDesc& d, int
           for (int32_t p = p0[j] + S + slot; p < p1[j]; p += S) {
             const XT vv = value_at<C>(a, p);
             XT xx[VEC];
-            load_x<XT, VEC>(X + static_cast<int64_t>(ld_mat<C::kNT>(a.colind + p)) * a.ldx, xx);
+            if constexpr (C::kHot) xx[0] = x_at<C>(a, X, ld_mat<C::kNT>(a.colind + p), a.ldx);
+            else load_x<XT, VEC>(X + static_cast<int64_t>(ld_mat<C::kNT>(a.colind + p)) * a.ldx, xx);
             if constexpr (C::kSave) save_x<C>(a, p, xx[0]);
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
@@ -516,7 +537,7 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
     XT xv[kStreamPer];
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u)
-      xv[u] = (base + u * kWG + t < total) ? X[static_cast<int64_t>(cA[u]) * a.ldx] : XT(0);
+      xv[u] = (base + u * kWG + t < total) ? x_at<C>(a, X, cA[u], a.ldx) : XT(0);
     if constexpr (C::kSave) {
 #pragma unroll
       for (int u = 0; u < kStreamPer; ++u) {
@@ -553,7 +574,7 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
       Comp cc;
       cc.init();
       for (int32_t p = p0; p < p1; ++p)
-        cc.add_prod(value_at<C>(a, p), X[static_cast<int64_t>(ld_mat<C::kNT>(a.colind + p)) * a.ldx]);
+        cc.add_prod(value_at<C>(a, p), x_at<C>(a, X, ld_mat<C::kNT>(a.colind + p), a.ldx));
       out[0] = static_cast<XT>(cc.value());
     } else {
       out[0] = acc;

@@ -206,6 +206,19 @@ class Plan:
             check(L.csr_plan_staged_pipeline(h, 1), "csr_plan_staged_pipeline")
         return self
 
+    def attach_hot_x(self, A: CSR, hot: int, xdtype=torch.float64) -> "Plan":
+        """Keep the x entries of the `hot` most-used columns in LDS for SpMV
+        through this plan (csr_plan_attach_hot_x).  Returns self."""
+        L = _lib.load()
+        _dev(A.rowptr, A.colind)
+        xt = _lib.SPX_F64 if xdtype == torch.float64 else _lib.SPX_F32
+        nb = ctypes.c_size_t()
+        check(L.csr_plan_hot_x_workspace_bytes(A.n, A.nnz, hot, ctypes.byref(nb)), "csr_plan_hot_x_workspace_bytes")
+        self.hot_workspace = _workspace(nb.value, A.device)
+        check(L.csr_plan_attach_hot_x(self.handle, A.n, A.nnz, _ptr(A.colind), hot, xt, _ptr(self.hot_workspace),
+                                      nb.value, _stream()), "csr_plan_attach_hot_x")
+        return self
+
     def staged_info(self) -> dict:
         a, b, c, d = (ctypes.c_int32() for _ in range(4))
         check(_lib.load().csr_plan_staged_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
