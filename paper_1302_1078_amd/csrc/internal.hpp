@@ -100,7 +100,8 @@ struct ProdArgs {
   const void* X;
   void* Y;
   int64_t ldx, ldy;
-  const void* X2;  // sampled dot: the second dense operand (n x k), or the saved gather
+  const void* X2;  // sampled dot: the second dense operand (n x k), or the saved gather;
+                   // hot-x SpMV: the compact hot x entries (ldx2 of them)
   int64_t ldx2;
   void* xsave;     // SpMV with save: x[colind[p]] is also stored at xsave[p] (XT)
   int32_t k;

@@ -1,8 +1,9 @@
 // product.hip -- fused, row-binned CSR products on gfx950:
 //   y <- A x  (SpMV, paper Sec. 3)        and        Y <- A X  (SpMM, Sec. 5)
-// plus the same traversal for the transpose gather (CSC index), and an SpMV
+// plus the same traversal for the transpose gather (CSC index), an SpMV
 // variant that also stores each gathered x[colind[p]] at position p for the
-// gradient with respect to the values.
+// gradient with respect to the values, and an SpMV variant that reads the
+// most-used columns' x entries from a compact copy (hot x, hot.hip).
 //
 // One launch covers every bin of a plan.  Workgroups [bins[i].blk_begin,
 // bins[i+1].blk_begin) serve bin i; long-row bins come first so that their
