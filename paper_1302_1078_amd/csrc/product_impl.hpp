@@ -66,6 +66,21 @@ __device__ __forceinline__ void load_x(const T* p, T (&out)[N]) {
   }
 }
 
+// G consecutive elements starting at p, G x sizeof(T) <= 16 bytes and p
+// aligned to that size: one load.
+template <bool NT, int G, typename T>
+__device__ __forceinline__ void load_group(const T* p, T (&out)[G]) {
+  static_assert(G * sizeof(T) <= 16, "one load per group");
+  if constexpr (G == 1) {
+    out[0] = ld_mat<NT>(p);
+  } else {
+    typedef typename VecT<T, G>::type V;
+    const V v = ld_mat<NT>(reinterpret_cast<const V*>(p));
+#pragma unroll
+    for (int i = 0; i < G; ++i) out[i] = v[i];
+  }
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void store_y(T* p, const T (&in)[N], bool nt) {
   if constexpr (N == 1) {
@@ -486,8 +501,40 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   // packed four to a register rather than the positions themselves.
   static_assert(kStreamPer % 4 == 0 && kStreamRows <= 256, "row indices packed as bytes");
   constexpr int kPack = kStreamPer / 4;
+  // A contiguous tile whose colind and values start 16-byte aligned (no value
+  // permutation, not the save variant) loads each lane's elements in groups
+  // of G consecutive nonzeros: one index load and one 16-byte value load per
+  // group (G = 2 for FP64 values, 4 for FP32 and BF16) instead of G of each.
+  // The address unit, the bound of these streams, is charged per lane
+  // address; each load still covers whole lines across the wavefront.
+  // Chunks then start at the aligned position P0 - (P0 mod G), so the first
+  // chunk also loads (and never sums) up to G - 1 elements of the rows before
+  // the tile; only chunks that end inside the tile take groups, the last one
+  // loads element by element, clamped.
+  constexpr int G = sizeof(typename C::VT) == 8 ? 2 : 4;
+  static_assert(kStreamPer % G == 0, "whole groups per chunk");
+  const bool grouped = !C::kSave && contig && !a.vperm &&
+                       ((reinterpret_cast<uintptr_t>(a.colind) | reinterpret_cast<uintptr_t>(a.values)) & 15) == 0;
+  const int32_t cs0 = (grouped && total > 0) ? -(P0 & (G - 1)) : 0;
+  auto grouped_chunk = [&](int32_t cs) { return grouped && cs + kStreamChunk <= total; };
   auto fetch = [&](int32_t base, int32_t (&cc)[kStreamPer], Raw (&vv)[kStreamPer],
                    uint32_t (&rows)[kPack]) {
+    if (grouped_chunk(base)) {
+#pragma unroll
+      for (int g = 0; g < kStreamPer / G; ++g) {
+        const int32_t q = P0 + base + g * G * kWG + G * t;
+        int32_t cg[G];
+        Raw vg[G];
+        load_group<C::kNT, G>(a.colind + q, cg);
+        load_group<C::kNT, G>(static_cast<const typename C::VT*>(a.values) + q, vg);
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+          cc[G * g + e] = cg[e];
+          vv[G * g + e] = vg[e];
+        }
+      }
+      return;
+    }
     int32_t jj[kStreamPer], pp[kStreamPer];
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u) jj[u] = min(base + u * kWG + t, total - 1);
@@ -527,17 +574,24 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
   int32_t cA[kStreamPer];
   Raw vA[kStreamPer];
   uint32_t rA[kPack];
-  if (total > 0) fetch(0, cA, vA, rA);
-  for (int32_t base = 0; base < total; base += kStreamChunk) {
+  if (total > 0) fetch(cs0, cA, vA, rA);
+  for (int32_t base = cs0; base < total; base += kStreamChunk) {
     const bool more = base + kStreamChunk < total;
     int32_t cB[kStreamPer];
     Raw vB[kStreamPer];
     uint32_t rB[kPack];
     if (more) fetch(base + kStreamChunk, cB, vB, rB);
     XT xv[kStreamPer];
+    const bool gd = grouped_chunk(base);
+    // element index of slot u of this chunk (only the elements of the tile,
+    // 0 <= j < total, gather x)
+    auto elem = [&](int u) {
+      return gd ? base + (u / G) * G * kWG + G * t + (u % G) : base + u * kWG + t;
+    };
 #pragma unroll
     for (int u = 0; u < kStreamPer; ++u)
-      xv[u] = (base + u * kWG + t < total) ? x_at<C>(a, X, cA[u], a.ldx) : XT(0);
+      xv[u] = (static_cast<uint32_t>(elem(u)) < static_cast<uint32_t>(total)) ? x_at<C>(a, X, cA[u], a.ldx)
+                                                                              : XT(0);
     if constexpr (C::kSave) {
 #pragma unroll
       for (int u = 0; u < kStreamPer; ++u) {
@@ -547,8 +601,14 @@ __device__ __forceinline__ void do_stream(const ProdArgs& a, const BinDesc& d, i
         save_x<C>(a, contig ? P0 + j : s_p0[r] + (j - s_off[r]), xv[u]);
       }
     }
+    if (gd) {
 #pragma unroll
-    for (int u = 0; u < kStreamPer; ++u) s_prod[u * kWG + t] = static_cast<XT>(VL::widen(vA[u])) * xv[u];
+      for (int u = 0; u < kStreamPer; ++u)
+        s_prod[(u / G) * G * kWG + G * t + (u % G)] = static_cast<XT>(VL::widen(vA[u])) * xv[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kStreamPer; ++u) s_prod[u * kWG + t] = static_cast<XT>(VL::widen(vA[u])) * xv[u];
+    }
     __syncthreads();
     const int32_t b0 = max(off, base) - base;
     const int32_t b1 = min(off + L, base + kStreamChunk) - base;
