@@ -287,6 +287,16 @@ def bench_c2(ctx, A1=None):
                                         "speedup_vs_default_plan": t / ts, **ps.staged_info(),
                                         "pipelined_us": tp * 1e6, "pipelined_speedup_vs_default_plan": t / tp}
                     del ps, pp, ys
+                    # rows ordered band by band of the bandwidth (row_period):
+                    # each XCD sweeps its own slab of the grid
+                    pb = spx.Plan.for_matrix(Aq, spx.banded_opts(Aq, k, vals.dtype))
+                    yb = torch.empty_like(yd)
+                    tb = float(ctx["timer"].run([lambda: spx.spmm(Aq, Xd, Y=yb, plan=pb)], ctx["fsteps"], 3)[:, 0].mean())
+                    r["banded_plan"] = {"us": tb * 1e6, "eff_gbs": b / tb / 1e9, "frac_hbm": b / tb / 1e9 / PEAK_HBM_GBS,
+                                        "speedup_vs_default_plan": t / tb, "row_period": int(pb.opts.row_period),
+                                        "equals_default_bitwise": bool(torch.equal(yb.view(torch.uint8),
+                                                                                   yd.view(torch.uint8)))}
+                    del pb, yb
                 if vname != "f64":
                     r["rel2_vs_gpu_fp64"] = max(rel2(yh[:, j], y3[:, j]) for j in range(k))
                     y5 = fp64_product(A.with_values(vals.double()), Xq64, k)

@@ -96,7 +96,17 @@ typedef struct spx_plan_opts {
                         * threads-per-core scaling, Sec. 4.2).  Rejected with
                         * SPX_ERR_UNSUPPORTED at launch if the device's LDS limits
                         * cannot express it. */
-  int32_t reserved[3];
+  int32_t row_period;  /* 0, or P > 0: inside each bin, rows are listed by band
+                        * floor(8 (r mod P) / P), then ascending.  The product
+                        * launch gives XCD j the j-th eighth of every bin's tiles,
+                        * so with P the matrix's bandwidth (csr_bandwidth, Sec.
+                        * 4.4) each XCD sweeps its own band of every period: on a
+                        * grid matrix a slab of the grid, whose X rows then stay in
+                        * that XCD's L2 from one period to the next instead of being
+                        * fetched again per neighbouring plane (the vector
+                        * re-transfers of Sec. 4.4 and Sec. 5).  P >= m gives the
+                        * ascending order.  Results are bitwise those of P = 0. */
+  int32_t reserved[2];
 } spx_plan_opts;
 
 typedef struct spx_plan spx_plan;   /* opaque host object */
@@ -413,6 +423,15 @@ spx_status csr_permute(int32_t m, int32_t nnz, const int32_t *rowptr, const int3
 spx_status csr_degree_order_workspace_bytes(int32_t n, int32_t nnz, size_t *bytes);
 spx_status csr_degree_order(int32_t n, int32_t nnz, const int32_t *colind, int32_t *perm, void *workspace,
                             size_t ws_bytes, void *stream);
+
+/* Bandwidth (Sec. 4.4): *bw_out (device int32) receives the largest distance
+ * |colind[p] - r| between a nonzero and the diagonal over all rows r (0 for a
+ * matrix without nonzeros), the row period to give a plan that orders a banded
+ * matrix's rows band by band (spx_plan_opts.row_period).  rowptr int32[m+1],
+ * colind int32[nnz] on the device, assumed valid (csr_validate).  One thread
+ * per row.  Asynchronous on `stream`. */
+spx_status csr_bandwidth(int32_t m, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
+                         int32_t *bw_out, void *stream);
 
 /* Vector access (Sec. 4.2, Sec. 4.4): the expected number of times x is moved
  * from memory when rows are dealt round-robin, in chunks of `chunk`

@@ -36,14 +36,16 @@ class PlanOpts(ctypes.Structure):
         ("max_k", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("occupancy", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("row_period", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
     def to_dict(self) -> dict:
         nb = self.nbins
         return {"nbins": nb, "upper": list(self.upper[:nb - 1]), "lanes": list(self.lanes[:nb]),
                 "split_chunk": self.split_chunk, "kahan_len": self.kahan_len,
-                "max_k": self.max_k, "flags": self.flags, "occupancy": self.occupancy}
+                "max_k": self.max_k, "flags": self.flags, "occupancy": self.occupancy,
+                "row_period": self.row_period}
 
     @classmethod
     def from_dict(cls, d: dict) -> "PlanOpts":
@@ -58,6 +60,7 @@ class PlanOpts(ctypes.Structure):
         o.max_k = int(d.get("max_k", 1))
         o.flags = int(d.get("flags", 0))
         o.occupancy = int(d.get("occupancy", 0))
+        o.row_period = int(d.get("row_period", 0))
         return o
 
 
@@ -121,6 +124,7 @@ SIGNATURES = {
     "csr_rcm": (ctypes.c_int, [i32, i32, i32, P, P, P]),
     "csr_degree_order_workspace_bytes": (ctypes.c_int, [i32, i32, SZ]),
     "csr_degree_order": (ctypes.c_int, [i32, i32, P, P, P, ctypes.c_size_t, P]),
+    "csr_bandwidth": (ctypes.c_int, [i32, i32, P, P, P, P]),
     "csr_permute_workspace_bytes": (ctypes.c_int, [i32, i32, SZ]),
     "csr_permute": (ctypes.c_int, [i32, i32, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]),
     "csr_vector_access": (ctypes.c_int, [i32, i32, i32, P, P, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]),

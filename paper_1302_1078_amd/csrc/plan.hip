@@ -4,7 +4,9 @@
 // Bin b holds rows with upper[b-1] < L <= upper[b] (the last bin is
 // unbounded).  row_perm lists the rows of bin 0, then bin 1, ..., ascending
 // inside each bin: a stable partition computed with per-tile counts, one
-// device scan, and a ballot-ranked scatter.
+// device scan, and a ballot-ranked scatter.  With a row period P > 0 the
+// partition key is (bin, band) with band = floor(8 (r mod P) / P), so a bin
+// lists band 0's rows, then band 1's, ..., each ascending.
 #include <new>
 
 #include "device.hpp"
@@ -17,9 +19,14 @@ namespace {
 constexpr int kRowsPerThread = 16;
 constexpr int kBinTile = kWG * kRowsPerThread;  // 4096 rows per workgroup
 
+constexpr int kBands = 8;  // one band of each row period per XCD
+constexpr int kMaxKeys = SPX_MAX_BINS * kBands;
+
 struct BinParams {
   int32_t nbins;
   int32_t upper[SPX_MAX_BINS];
+  int32_t period;  // 0: rows ascending inside a bin; P > 0: by band of r mod P, then ascending
+  int32_t nkeys;   // nbins, or nbins x kBands with a period
 };
 
 __device__ __forceinline__ int bin_of(int32_t L, const BinParams& bp) {
@@ -28,20 +35,27 @@ __device__ __forceinline__ int bin_of(int32_t L, const BinParams& bp) {
   return b;
 }
 
+// Partition key of row i (length L): its bin, and with a period its band.
+__device__ __forceinline__ int key_of(int64_t i, int32_t L, const BinParams& bp) {
+  const int b = bin_of(L, bp);
+  if (bp.period <= 0) return b;
+  return b * kBands + static_cast<int>((i % bp.period) * kBands / bp.period);
+}
+
 __global__ __launch_bounds__(kWG) void k_bin_count(const int32_t* __restrict__ rowptr, int32_t m,
                                                    const BinParams bp,
                                                    int32_t* __restrict__ counts, int nblk) {
-  __shared__ int32_t cnt[SPX_MAX_BINS];
+  __shared__ int32_t cnt[kMaxKeys];
   const int t = threadIdx.x;
-  if (t < SPX_MAX_BINS) cnt[t] = 0;
+  if (t < kMaxKeys) cnt[t] = 0;
   __syncthreads();
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kBinTile;
   for (int j = 0; j < kRowsPerThread; ++j) {
     const int64_t i = base + j * kWG + t;
-    if (i < m) atomicAdd(&cnt[bin_of(rowptr[i + 1] - rowptr[i], bp)], 1);
+    if (i < m) atomicAdd(&cnt[key_of(i, rowptr[i + 1] - rowptr[i], bp)], 1);
   }
   __syncthreads();
-  if (t < bp.nbins) counts[static_cast<int64_t>(t) * nblk + blockIdx.x] = cnt[t];
+  if (t < bp.nkeys) counts[static_cast<int64_t>(t) * nblk + blockIdx.x] = cnt[t];
 }
 
 // Stable scatter: rows ranked in (round, wave, lane) order = ascending row.
@@ -49,19 +63,19 @@ __global__ __launch_bounds__(kWG) void k_bin_scatter(const int32_t* __restrict__
                                                      const BinParams bp,
                                                      const int32_t* __restrict__ offs, int nblk,
                                                      int32_t* __restrict__ row_perm) {
-  __shared__ int32_t run[SPX_MAX_BINS];
-  __shared__ int32_t wcnt[kWG / kWave][SPX_MAX_BINS];
+  __shared__ int32_t run[kMaxKeys];
+  __shared__ int32_t wcnt[kWG / kWave][kMaxKeys];
   const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  if (t < bp.nbins) run[t] = offs[static_cast<int64_t>(t) * nblk + blockIdx.x];
+  if (t < bp.nkeys) run[t] = offs[static_cast<int64_t>(t) * nblk + blockIdx.x];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kBinTile;
   __syncthreads();
   for (int j = 0; j < kRowsPerThread; ++j) {
     const int64_t i = base + j * kWG + t;
     const bool valid = i < m;
-    const int b = valid ? bin_of(rowptr[i + 1] - rowptr[i], bp) : -1;
+    const int b = valid ? key_of(i, rowptr[i + 1] - rowptr[i], bp) : -1;
     int rank = 0;
-    for (int q = 0; q < bp.nbins; ++q) {
+    for (int q = 0; q < bp.nkeys; ++q) {
       const uint64_t mask = __ballot(b == q);
       if (b == q) rank = __popcll(mask & lt_mask);
       if (lane == 0) wcnt[w][q] = __popcll(mask);
@@ -73,7 +87,7 @@ __global__ __launch_bounds__(kWG) void k_bin_scatter(const int32_t* __restrict__
       row_perm[pos] = static_cast<int32_t>(i);
     }
     __syncthreads();
-    if (t < bp.nbins) {
+    if (t < bp.nkeys) {
       int32_t add = 0;
       for (int v = 0; v < kWG / kWave; ++v) add += wcnt[v][t];
       run[t] += add;
@@ -82,10 +96,11 @@ __global__ __launch_bounds__(kWG) void k_bin_scatter(const int32_t* __restrict__
   }
 }
 
-__global__ void k_bin_off(const int32_t* __restrict__ offs, int nblk, int32_t nbins, int32_t m,
-                          int32_t* __restrict__ bin_off) {
+// Bin b begins at its first key, b x keys_per_bin.
+__global__ void k_bin_off(const int32_t* __restrict__ offs, int nblk, int32_t nbins, int32_t keys_per_bin,
+                          int32_t m, int32_t* __restrict__ bin_off) {
   const int b = threadIdx.x;
-  if (b < nbins) bin_off[b] = (nblk > 0) ? offs[static_cast<int64_t>(b) * nblk] : 0;
+  if (b < nbins) bin_off[b] = (nblk > 0) ? offs[static_cast<int64_t>(b) * keys_per_bin * nblk] : 0;
   if (b == nbins) bin_off[b] = m;
 }
 
@@ -137,6 +152,8 @@ struct PlanWs {
 
 bool has_split(const spx_plan_opts& o) { return o.lanes[o.nbins - 1] == 0; }
 
+int32_t keys_per_bin(const spx_plan_opts& o) { return o.row_period > 0 ? kBands : 1; }
+
 // Upper bounds on split rows and segments, from sizes and options only.
 void split_bounds(int32_t m, int32_t nnz, const spx_plan_opts& o, int64_t* nsplit, int64_t* nseg) {
   if (!has_split(o)) {
@@ -159,13 +176,14 @@ PlanWs carve_plan(void* ws, int32_t m, int32_t nnz, const spx_plan_opts& o, size
   PlanWs w;
   w.row_perm = cv.take<int32_t>(m > 0 ? m : 1);
   w.prange = cv.take<int32_t>(2 * static_cast<int64_t>(m > 0 ? m : 1));
-  w.counts = cv.take<int32_t>(nblk * o.nbins + 1);
+  w.counts = cv.take<int32_t>(nblk * o.nbins * keys_per_bin(o) + 1);
   w.bin_off = cv.take<int32_t>(SPX_MAX_BINS + 1);
   w.seg_first = cv.take<int32_t>(nsplit + 1);
   w.seg_row = cv.take<int32_t>(nseg + 1);
   w.counters = cv.take<int32_t>(nsplit + 1);
   w.partials = cv.take<double>((nseg + 1) * o.max_k);
-  const int64_t sc = nblk * o.nbins > nsplit ? nblk * o.nbins : nsplit;
+  const int64_t nk = nblk * o.nbins * keys_per_bin(o);
+  const int64_t sc = nk > nsplit ? nk : nsplit;
   w.scan = cv.take<char>(scan_workspace_bytes(sc + 1));
   *bytes = cv.used;
   return w;
@@ -193,6 +211,7 @@ spx_status check_opts(const spx_plan_opts* o) {
   if (o->max_k < 1) return fail(SPX_ERR_INVALID, "max_k < 1");
   if (o->occupancy < 0 || o->occupancy > 8)
     return fail(SPX_ERR_INVALID, "occupancy=%d outside [0, 8]", o->occupancy);
+  if (o->row_period < 0) return fail(SPX_ERR_INVALID, "row_period=%d < 0", o->row_period);
   return SPX_OK;
 }
 
@@ -279,12 +298,14 @@ extern "C" spx_status csr_plan_create(int32_t m, int32_t n, int32_t nnz, const i
   BinParams bp{};
   bp.nbins = opts->nbins;
   for (int b = 0; b < SPX_MAX_BINS; ++b) bp.upper[b] = opts->upper[b];
+  bp.period = opts->row_period;
+  bp.nkeys = opts->nbins * keys_per_bin(*opts);
 
   if (nblk > 0) {
     k_bin_count<<<static_cast<unsigned>(nblk), kWG, 0, st>>>(rowptr, m, bp, w.counts,
                                                              static_cast<int>(nblk));
     SPX_LAUNCHED("k_bin_count");
-    s = exclusive_scan_i32(w.counts, w.counts, nblk * opts->nbins, nullptr, w.scan, st);
+    s = exclusive_scan_i32(w.counts, w.counts, nblk * bp.nkeys, nullptr, w.scan, st);
     if (s != SPX_OK) return s;
     k_bin_scatter<<<static_cast<unsigned>(nblk), kWG, 0, st>>>(rowptr, m, bp, w.counts,
                                                                static_cast<int>(nblk), w.row_perm);
@@ -292,7 +313,8 @@ extern "C" spx_status csr_plan_create(int32_t m, int32_t n, int32_t nnz, const i
     k_prange<<<grid_for(m), 256, 0, st>>>(rowptr, w.row_perm, m, reinterpret_cast<int2*>(w.prange));
     SPX_LAUNCHED("k_prange");
   }
-  k_bin_off<<<1, 64, 0, st>>>(w.counts, static_cast<int>(nblk), opts->nbins, m, w.bin_off);
+  k_bin_off<<<1, 64, 0, st>>>(w.counts, static_cast<int>(nblk), opts->nbins, keys_per_bin(*opts), m,
+                              w.bin_off);
   SPX_LAUNCHED("k_bin_off");
 
   spx_plan* p = new (std::nothrow) spx_plan();

@@ -298,6 +298,25 @@ __global__ void k_degree_keys(const int32_t* __restrict__ cnt, int32_t n, uint32
   idx[j] = static_cast<int32_t>(j);
 }
 
+// Bandwidth (Sec. 4.4): max |colind[p] - r| over the nonzeros of each row r;
+// a wavefront maximum, then one atomic per wavefront into a zeroed *out.
+__global__ void k_bandwidth(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind, int32_t m,
+                            int32_t* __restrict__ out) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  int32_t best = 0;
+  if (r < m) {
+    const int32_t p1 = rowptr[r + 1];
+    for (int32_t p = rowptr[r]; p < p1; ++p) {
+      const int64_t d = static_cast<int64_t>(colind[p]) - r;
+      const int64_t a = d < 0 ? -d : d;
+      best = max(best, static_cast<int32_t>(a < INT32_MAX ? a : INT32_MAX));
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off, kWave));
+  if (threadIdx.x % kWave == 0 && best > 0) atomicMax(out, best);
+}
+
 }  // namespace
 }  // namespace spx
 
@@ -385,4 +404,23 @@ extern "C" spx_status csr_permute(int32_t m, int32_t nnz, const int32_t* rowptr,
   }
   return csr_from_coo(m, m, nnz, r, c, v, rowptr_out, colind_out, values_out, nnz_out, w,
                       ws_bytes - static_cast<size_t>(w - static_cast<char*>(workspace)), stream);
+}
+
+extern "C" spx_status csr_bandwidth(int32_t m, int32_t nnz, const int32_t* rowptr, const int32_t* colind,
+                                    int32_t* bw_out, void* stream) {
+  if (m < 0 || nnz < 0) return fail(SPX_ERR_INVALID, "csr_bandwidth: negative size");
+  {
+    const spx_status s_nnz = check_nnz(nnz, "csr_bandwidth");
+    if (s_nnz != SPX_OK) return s_nnz;
+  }
+  if (!bw_out || (m > 0 && !rowptr) || (nnz > 0 && !colind))
+    return fail(SPX_ERR_INVALID, "csr_bandwidth: null pointer");
+  hipStream_t st = as_stream(stream);
+  k_set_i32<<<1, 64, 0, st>>>(bw_out, 1, 0);
+  SPX_LAUNCHED("k_set_i32");
+  if (m > 0 && nnz > 0) {
+    k_bandwidth<<<blocks_for(m), 256, 0, st>>>(rowptr, colind, m, bw_out);
+    SPX_LAUNCHED("k_bandwidth");
+  }
+  return SPX_OK;
 }

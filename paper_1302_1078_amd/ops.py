@@ -480,6 +480,23 @@ def degree_order(A: CSR) -> torch.Tensor:
     return perm[:A.n]
 
 
+def bandwidth(A: CSR) -> int:
+    """Largest |colind[p] - row| over the nonzeros (csr_bandwidth, device, Sec. 4.4)."""
+    L = _lib.load()
+    _dev(A.rowptr, A.colind)
+    out = torch.empty(1, dtype=torch.int32, device=A.device)
+    check(L.csr_bandwidth(A.m, A.nnz, _ptr(A.rowptr), _ptr(A.colind), _ptr(out), _stream()), "csr_bandwidth")
+    return int(out.item())
+
+
+def banded_opts(A: CSR, k: int = 1, vtype=torch.float64) -> PlanOpts:
+    """Default plan options with rows ordered band by band of the matrix's
+    bandwidth (spx_plan_opts.row_period): each XCD sweeps its own band."""
+    o = default_opts(k, vtype)
+    o.row_period = bandwidth(A)
+    return o
+
+
 def permute(A: CSR, perm: torch.Tensor) -> CSR:
     """P A P^T for a device permutation perm[new] = old (csr_permute; FP64 values)."""
     L = _lib.load()

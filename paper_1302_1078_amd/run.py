@@ -35,6 +35,8 @@ def main(argv=None):
                     help="SpMM through a staged plan (each row tile's X window in LDS) instead of the default")
     ap.add_argument("--pipelined", action="store_true",
                     help="with --staged: the persistent double-buffered staged kernel")
+    ap.add_argument("--banded", action="store_true",
+                    help="rows ordered band by band of the matrix's bandwidth (plan row_period)")
     ap.add_argument("--probe-copy-mib", type=int, default=0)
     ap.add_argument("--no-flush", action="store_true")
     ap.add_argument("--bandwidth", action="store_true",
@@ -104,7 +106,7 @@ def main(argv=None):
         print(f"ran {args.op} on {args.workload} ({A.nnz} indices) x{args.reps}", flush=True)
         return
     plans = [ops.Plan.staged(A, k, xt, pipelined=args.pipelined) if args.staged
-             else ops.Plan.for_matrix(A, ops.default_opts(k, vt))]
+             else ops.Plan.for_matrix(A, ops.banded_opts(A, k, vt) if args.banded else ops.default_opts(k, vt))]
     for l in [int(s) for s in args.lanes.split(",") if s.strip()]:
         plans.append(ops.Plan.for_matrix(A, PlanOpts.from_dict({"nbins": 1, "upper": [], "lanes": [l],
                                                                  "split_chunk": 4096, "max_k": k})))

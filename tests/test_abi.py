@@ -92,12 +92,21 @@ def test_occupancy_option_checked():
     assert b"occupancy" in L.spx_last_error()
     o.occupancy = 4
     assert L.csr_plan_workspace_bytes(100, 1000, ctypes.byref(o), ctypes.byref(nb)) == 0
+    o.row_period = -1
+    assert L.csr_plan_workspace_bytes(100, 1000, ctypes.byref(o), ctypes.byref(nb)) != 0
+    assert b"row_period" in L.spx_last_error()
+    o.row_period = 0
+    assert L.csr_plan_workspace_bytes(100000, 1000000, ctypes.byref(o), ctypes.byref(nb)) == 0
+    plain = nb.value
+    o.row_period = 1000   # eight band counts per bin and tile
+    assert L.csr_plan_workspace_bytes(100000, 1000000, ctypes.byref(o), ctypes.byref(nb)) == 0
+    assert nb.value > plain
 
 
 def test_plan_opts_roundtrip_and_autotune_cache(tmp_path):
     from paper_1302_1078_amd import _lib, autotune
     d = {"nbins": 3, "upper": [4, 64], "lanes": [4, 64, 0], "split_chunk": 1024, "kahan_len": 256,
-         "max_k": 8, "flags": 0, "occupancy": 3}
+         "max_k": 8, "flags": 0, "occupancy": 3, "row_period": 16384}
     assert _lib.PlanOpts.from_dict(d).to_dict() == d
     p = tmp_path / "c.json"
     p.write_text("{broken")
