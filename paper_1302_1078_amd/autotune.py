@@ -1,5 +1,5 @@
 """Per-matrix autotuner for plan options (bin thresholds, lanes per row,
-split chunk).
+split chunk, and for single SpMM products of banded matrices the row order).
 
 Candidates are timed on the GPU with HIP events: each sample brackets `calls`
 back-to-back launches of csr_spmv / csr_spmm on the current stream (so the
@@ -23,12 +23,12 @@ import os
 import torch
 
 from ._lib import SPX_FLAG_KEEP_STREAM, PlanOpts
-from .ops import CSR, Plan, default_opts, spmm, spmv
+from .ops import CSR, Plan, bandwidth, default_opts, spmm, spmv
 
 STREAM = 512  # SPX_LANES_STREAM
 
 
-TUNER_VERSION = 2  # part of the cache key: decisions of other tuner versions are not reused
+TUNER_VERSION = 3  # part of the cache key: decisions of other tuner versions are not reused
 
 
 def structure_key(A: CSR, k: int, setting: str = "") -> str:
@@ -78,6 +78,17 @@ def candidates(k: int, vdtype=torch.float64) -> list:
                                  "max_k": k, "flags": 0})
     out.append(coarse)
     return out
+
+
+def banded_candidate(A: CSR, base: PlanOpts) -> PlanOpts | None:
+    """base with rows ordered band by band of A's bandwidth (row_period), or
+    None when the bandwidth is 0 or leaves the rows ascending (>= m)."""
+    P = bandwidth(A)
+    if P <= 0 or P >= A.m:
+        return None
+    c = _copy(base)
+    c.row_period = P
+    return c
 
 
 def load_cache(path: str | None) -> dict:
@@ -133,7 +144,14 @@ def tune(A: CSR, X: torch.Tensor, reps: int = 5, cache_path: str | None = None,
         o = _valid(cache[key])
         if o is not None:
             return o, {"cached": True, "ms": cache[key].get("ms")}
-    cands = cands if cands is not None else candidates(k, A.values.dtype)
+    if cands is None:
+        cands = candidates(k, A.values.dtype)
+        if not batch and k > 1:
+            # a batch deals tiles across matrices, so the per-XCD bands of a
+            # row period only apply to single products
+            b = banded_candidate(A, cands[0])
+            if b is not None:
+                cands.append(b)
     timed = []
     for o in cands:
         c = _copy(o)

@@ -70,3 +70,27 @@ def test_cache_key_carries_settings(monkeypatch, fake_matrix, tmp_path):
     _, rep3, seen = run_tune(monkeypatch, fake_matrix, times, cache_path=cache, margin=0.01)
     assert not rep3["cached"] and seen  # other settings: tuned again
     assert len(json.load(open(cache))) == 2
+
+
+def test_banded_candidate_for_single_spmm(monkeypatch, fake_matrix):
+    """Single SpMM products (batch=False, k > 1) also time the default plan with
+    rows ordered by the matrix's bandwidth; batches and SpMV do not, nor does a
+    bandwidth that leaves the order ascending."""
+    from paper_1302_1078_amd import autotune
+    seen = []
+    monkeypatch.setattr(autotune, "time_opts", lambda A_, X_, o, reps=5, calls=8: seen.append(o) or 1.0)
+    monkeypatch.setattr(autotune, "bandwidth", lambda A_: 1)
+    X = torch.ones((3, 4), dtype=torch.float64)
+    n = len(autotune.candidates(4))
+    autotune.tune(fake_matrix, X, batch=False)
+    assert len(seen) == n + 1 and seen[-1].row_period == 1 and all(o.row_period == 0 for o in seen[:-1])
+    seen.clear()
+    autotune.tune(fake_matrix, X, batch=True)
+    assert len(seen) == n and all(o.row_period == 0 for o in seen)
+    seen.clear()
+    autotune.tune(fake_matrix, torch.ones(3, dtype=torch.float64), batch=False)
+    assert all(o.row_period == 0 for o in seen)
+    seen.clear()
+    monkeypatch.setattr(autotune, "bandwidth", lambda A_: 3)   # >= m: ascending anyway
+    autotune.tune(fake_matrix, X, batch=False)
+    assert len(seen) == n
