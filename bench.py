@@ -537,8 +537,40 @@ def bench_bcsr(ctx, A1=None):
                 "bytes": B.stored_bytes(), "max_rel_diff_vs_csr": err}
             del B
             torch.cuda.empty_cache()
+        if name.startswith("stencil"):
+            rows["spmm"] = bcsr_spmm_rows(ctx, A)
         out[name] = rows
     return out
+
+
+def bcsr_spmm_rows(ctx, A):
+    """SpMM (Sec. 5) through a x 1 register blocks against the CSR kernel with
+    the default and the banded plan, FP64, flushed, per k: time, and the
+    largest difference to the default CSR product relative to its largest
+    entry (the sums run in another order)."""
+    torch, spx, spgen, dev = ctx["torch"], ctx["spx"], ctx["spgen"], ctx["dev"]
+    res = {}
+    for k in (8, 16, 32):
+        X = torch.from_numpy(spgen.uniform(A.n * k, 31, spgen.TAG_X).reshape(A.n, k)).to(dev)
+        Y = torch.empty((A.m, k), dtype=torch.float64, device=dev)
+        p0 = spx.Plan.for_matrix(A, spx.default_opts(k))
+        pb = spx.Plan.for_matrix(A, spx.banded_opts(A, k))
+        t0 = float(ctx["timer"].run([lambda: spx.spmm(A, X, Y=Y, plan=p0)], ctx["fsteps"], 3)[:, 0].mean())
+        ref = Y.clone()
+        tb = float(ctx["timer"].run([lambda: spx.spmm(A, X, Y=Y, plan=pb)], ctx["fsteps"], 3)[:, 0].mean())
+        r = {"csr_us": t0 * 1e6, "csr_banded_us": tb * 1e6}
+        for a in (2, 4, 8):
+            B = spx.BCSR.from_csr(A, a, 1)
+            t = float(ctx["timer"].run([lambda: spx.bcsr_spmm(B, X, Y=Y)], ctx["fsteps"], 3)[:, 0].mean())
+            r[f"bcsr_{a}x1"] = {"us": t * 1e6, "speedup_vs_csr": t0 / t, "gflops": 2 * A.nnz * k / t / 1e9,
+                                "density": A.nnz / (B.nblocks * a), "stored_bytes": B.stored_bytes(),
+                                "max_rel_diff_vs_csr": float((Y - ref).abs().max() / ref.abs().max())}
+            del B
+            torch.cuda.empty_cache()
+        res[f"k{k}"] = r
+        del X, Y, ref, p0, pb
+        torch.cuda.empty_cache()
+    return res
 
 
 # ---------------------------------------------------------------- c3

@@ -491,6 +491,20 @@ spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int32_t bitmap,
                      const int32_t *browptr, const int32_t *bcol, const double *bvals, const uint64_t *bmask,
                      const int32_t *boff, const double *x, double *y, int32_t lanes, void *stream);
 
+/* Y <- A X with A in register-blocked form (Sec. 4.5) applied to the
+ * multi-vector product (Sec. 5): dense a x 1 blocks (a in {2, 4, 8}, b = 1,
+ * bitmap form not taken), FP64.  Each X row a block refers to is gathered
+ * once and multiplied into a rows of Y, so a banded matrix whose consecutive
+ * rows share columns gathers fewer X rows than through CSR, at the price of
+ * the block's explicit zeros.  X f64 n x k, row stride ldx >= k; Y f64 m x k,
+ * row stride ldy >= k, overwritten.  `slots` blocks of a block row are
+ * walked at a time (a power of two; 0 picks it from the mean blocks per
+ * block row); k above 64 runs in column slabs.  Asynchronous on `stream`.
+ * Other block shapes return SPX_ERR_UNSUPPORTED. */
+spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int32_t nblocks, const int32_t *browptr,
+                     const int32_t *bcol, const double *bvals, int32_t k, const double *X, int64_t ldx,
+                     double *Y, int64_t ldy, int32_t slots, void *stream);
+
 /* ---------------------------------------------------------------- probes
  * Memory-system probes (the GPU counterparts of the paper's read / write
  * bandwidth microbenchmarks, Sec. 2.1 and 2.2), used to calibrate measured

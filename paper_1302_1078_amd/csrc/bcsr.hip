@@ -11,7 +11,10 @@
 // block); it is one-time and untimed, as in the paper.  The product gives
 // each block row to a group of G lanes; every lane multiplies whole blocks
 // (A accumulators, the B-element slice of x loaded once per block) and the
-// group reduces its A partial sums.
+// group reduces its A partial sums.  The multi-vector product (a x 1 dense
+// blocks) lays lanes out as the CSR SpMM does, KL lanes x VEC columns per X
+// row and S slots walking a block row's blocks, and keeps a x VEC
+// accumulators per lane, so each X row gathered serves a rows of Y.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -266,6 +269,163 @@ spx_status launch_bcsr(int a, int b, const BcsrArgs& p, unsigned grid, hipStream
   return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmv: block %dx%d", a, b);
 }
 
+// ---------------------------------------------------------------- multi-vector product
+
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// VEC consecutive elements of an X row (16-byte aligned when VEC = 2)
+template <int VEC>
+__device__ __forceinline__ void ld_xrow(const double* q, double (&out)[VEC]) {
+  if constexpr (VEC == 1) {
+    out[0] = *q;
+  } else {
+    const dbl2 w = *reinterpret_cast<const dbl2*>(q);
+    out[0] = w[0];
+    out[1] = w[1];
+  }
+}
+
+struct BcsrMmArgs {
+  const int32_t* browptr;
+  const int32_t* bcol;
+  const double* bvals;
+  const double* X;
+  double* Y;
+  int64_t ldx, ldy;
+  int32_t m, mb, k;  // k: columns of this launch (a slab of at most KL x VEC)
+  int32_t slots;     // S: slots per block row, S x KL <= 64
+};
+
+// Y[A R + r, :] = sum over the blocks q of block row R of bvals[A q + r] X[bcol[q], :].
+// Every round a slot takes U blocks (q, q + S, ...); the KL lanes of the
+// slot share that round's block columns and values: lane kl loads items kl,
+// kl + KL, ... and the slot reads them back with cross-lane moves, so the
+// address unit sees one lane per item instead of KL.  The next round's
+// columns and values are loaded after this round's X gathers are issued:
+// loads complete in issue order, so waiting for the gathers does not wait
+// for them, and a round costs one memory round trip instead of two.
+template <int A, int KL, int VEC>
+__global__ __launch_bounds__(kWG) void k_bcsr_spmm(const BcsrMmArgs p) {
+  constexpr int U = (A >= 8) ? 2 : 4;
+  constexpr int PC = (U + KL - 1) / KL;      // block columns per lane
+  constexpr int PV = (U * A + KL - 1) / KL;  // values per lane
+  const int S = p.slots;
+  const int G = S * KL;
+  const int t = threadIdx.x, lane = t % kWave;
+  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t R = (tile * kWG + t) / G;
+  const int kl = lane % KL, slot = (lane % G) / KL;
+  const int sbase = lane - kl;
+  const int col = kl * VEC;
+  const bool active = R < p.mb;
+  const bool colok = col < p.k;
+  double acc[A][VEC];
+#pragma unroll
+  for (int r = 0; r < A; ++r)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[r][e] = 0.0;
+  int32_t q0 = 0, q1 = 0;
+  if (active) {
+    q0 = p.browptr[R];
+    q1 = p.browptr[R + 1];
+  }
+  // block columns and values of the round starting at q (zero past q1)
+  auto fetch = [&](int32_t q, int32_t (&cl)[PC], double (&vl)[PV]) {
+#pragma unroll
+    for (int j = 0; j < PC; ++j) {
+      const int u = kl + j * KL;
+      const int32_t qq = q + u * S;
+      cl[j] = (u < U && qq < q1) ? __builtin_nontemporal_load(p.bcol + qq) : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < PV; ++j) {
+      const int i = kl + j * KL, u = i / A, r = i % A;
+      const int32_t qq = q + u * S;
+      vl[j] = (i < U * A && qq < q1) ? __builtin_nontemporal_load(p.bvals + static_cast<int64_t>(qq) * A + r) : 0.0;
+    }
+  };
+  int32_t clA[PC];
+  double vlA[PV];
+  const int32_t qs = q0 + slot;
+  if (qs < q1) fetch(qs, clA, vlA);
+  for (int32_t q = qs; q < q1; q += U * S) {
+    int32_t c[U];
+    bool h[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      h[u] = q + u * S < q1;
+      c[u] = __shfl(clA[u / KL], sbase + u % KL, kWave);
+    }
+    double xv[U][VEC];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (h[u] && colok) {
+        ld_xrow<VEC>(p.X + static_cast<int64_t>(c[u]) * p.ldx + col, xv[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) xv[u][e] = 0.0;
+      }
+    }
+    const bool more = q + U * S < q1;  // the same for the KL lanes of a slot
+    int32_t clB[PC];
+    double vlB[PV];
+    if (more) fetch(q + U * S, clB, vlB);
+    double v[U * A];
+#pragma unroll
+    for (int i = 0; i < U * A; ++i) v[i] = __shfl(vlA[i / KL], sbase + i % KL, kWave);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < A; ++r)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (h[u]) acc[r][e] = __builtin_fma(v[u * A + r], xv[u][e], acc[r][e]);
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < PC; ++j) clA[j] = clB[j];
+#pragma unroll
+      for (int j = 0; j < PV; ++j) vlA[j] = vlB[j];
+    }
+  }
+  // slots of a block row are lanes KL apart inside one wavefront
+#pragma unroll
+  for (int r = 0; r < A; ++r)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      for (int off = KL; off < G; off <<= 1) acc[r][e] += __shfl_xor(acc[r][e], off, kWave);
+  if (active && slot == 0 && colok) {
+#pragma unroll
+    for (int r = 0; r < A; ++r) {
+      const int64_t row = R * A + r;
+      if (row < p.m) {
+        double* y = p.Y + row * p.ldy + col;
+        if constexpr (VEC == 1) {
+          y[0] = acc[r][0];
+        } else {
+          dbl2 w;
+          w[0] = acc[r][0];
+          w[1] = acc[r][1];
+          *reinterpret_cast<dbl2*>(y) = w;
+        }
+      }
+    }
+  }
+}
+
+template <int A>
+spx_status launch_bcsr_mm_a(int kl, int vec, const BcsrMmArgs& p, unsigned grid, hipStream_t st) {
+#define SPX_MMCASE(KL_, VEC_)                                    \
+  if (kl == KL_ && vec == VEC_) {                                \
+    k_bcsr_spmm<A, KL_, VEC_><<<grid, kWG, 0, st>>>(p);          \
+    SPX_LAUNCHED("k_bcsr_spmm");                                 \
+    return SPX_OK;                                               \
+  }
+  SPX_MMCASE(1, 1) SPX_MMCASE(2, 1) SPX_MMCASE(4, 1) SPX_MMCASE(8, 1) SPX_MMCASE(16, 1) SPX_MMCASE(32, 1)
+  SPX_MMCASE(1, 2) SPX_MMCASE(2, 2) SPX_MMCASE(4, 2) SPX_MMCASE(8, 2) SPX_MMCASE(16, 2) SPX_MMCASE(32, 2)
+#undef SPX_MMCASE
+  return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: lanes %d x %d", kl, vec);
+}
+
 }  // namespace
 }  // namespace spx
 
@@ -364,4 +524,53 @@ extern "C" spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int3
   hipStream_t st = as_stream(stream);
   return bitmap ? launch_bcsr<true>(a, b, p, static_cast<unsigned>(grid), st)
                 : launch_bcsr<false>(a, b, p, static_cast<unsigned>(grid), st);
+}
+
+extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int32_t nblocks,
+                                const int32_t* browptr, const int32_t* bcol, const double* bvals, int32_t k,
+                                const double* X, int64_t ldx, double* Y, int64_t ldy, int32_t slots,
+                                void* stream) {
+  if (m < 0 || n < 0 || nblocks < 0 || k < 0) return fail(SPX_ERR_INVALID, "bcsr_spmm: negative size");
+  if (b != 1 || (a != 2 && a != 4 && a != 8))
+    return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: block %dx%d (a in {2, 4, 8}, b = 1, dense form)", a, b);
+  if (m == 0 || k == 0) return SPX_OK;
+  if (ldx < k || ldy < k) return fail(SPX_ERR_INVALID, "bcsr_spmm: ldx=%lld ldy=%lld < k=%d",
+                                      static_cast<long long>(ldx), static_cast<long long>(ldy), k);
+  if (!browptr || !Y || (nblocks > 0 && (!bcol || !bvals || !X))) return fail(SPX_ERR_INVALID, "bcsr_spmm: null pointer");
+  const int32_t mb = (m + a - 1) / a;
+  auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+  const int vec = (k % 2 == 0 && ldx % 2 == 0 && ldy % 2 == 0 && al16(X) && al16(Y)) ? 2 : 1;
+  const int width = 32 * vec;  // columns per launch
+  hipStream_t st = as_stream(stream);
+  for (int32_t c0 = 0; c0 < k; c0 += width) {
+    const int32_t kc = (k - c0 < width) ? (k - c0) : width;
+    const int per = (kc + vec - 1) / vec;
+    int kl = 1;
+    while (kl < per) kl <<= 1;
+    int S = slots;
+    if (S <= 0) {
+      // 16 to 32 lanes per block row measured best on the 27-point stencil
+      // (k = 8 to 32: 4 slots below 16 lanes per X row, 2 from 16 on; one
+      // slot, a wavefront per eight block rows, ran 1.5-2x slower); fewer
+      // when a block row holds less than a round of blocks per slot
+      const int U = (a >= 8) ? 2 : 4;
+      const double mean = static_cast<double>(nblocks) / mb;
+      S = (kl >= 16) ? 2 : 4;
+      if (S * kl > kWave) S = kWave / kl;
+      while (S > 1 && S * U > mean) S >>= 1;
+    }
+    if ((S & (S - 1)) || S * kl > kWave)
+      return fail(SPX_ERR_INVALID, "bcsr_spmm: slots=%d with %d lanes per X row (power of two, <= 64 lanes)", S, kl);
+    BcsrMmArgs p{browptr, bcol, bvals, X + c0, Y + c0, ldx, ldy, m, mb, kc, S};
+    const int64_t threads = static_cast<int64_t>(mb) * S * kl;
+    int64_t grid = (threads + kWG - 1) / kWG;
+    grid = (grid + 7) / 8 * 8;  // whole eighths: XCD j serves the j-th eighth of the block rows
+    if (grid > 0x7fffffff) return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: grid too large");
+    spx_status s = SPX_OK;
+    if (a == 2) s = launch_bcsr_mm_a<2>(kl, vec, p, static_cast<unsigned>(grid), st);
+    else if (a == 4) s = launch_bcsr_mm_a<4>(kl, vec, p, static_cast<unsigned>(grid), st);
+    else s = launch_bcsr_mm_a<8>(kl, vec, p, static_cast<unsigned>(grid), st);
+    if (s != SPX_OK) return s;
+  }
+  return SPX_OK;
 }

@@ -620,6 +620,24 @@ def bcsr_spmv(B: BCSR, x: torch.Tensor, y: torch.Tensor | None = None, lanes: in
     return y
 
 
+def bcsr_spmm(B: BCSR, X: torch.Tensor, Y: torch.Tensor | None = None, slots: int = 0) -> torch.Tensor:
+    """Y <- A X for a register-blocked A of a x 1 dense blocks (bcsr_spmm), FP64;
+    X n x k and Y m x k row-major (row strides taken from the tensors)."""
+    _dev(X)
+    if X.dtype != torch.float64 or X.dim() != 2 or X.shape[0] != B.n or X.stride(1) != 1:
+        raise ValueError("X must be float64, n x k, unit column stride")
+    if B.bitmap:
+        raise ValueError("bcsr_spmm takes the dense block form")
+    k = X.shape[1]
+    if Y is None:
+        Y = torch.empty((B.m, k), dtype=torch.float64, device=X.device)
+    if Y.dtype != torch.float64 or Y.dim() != 2 or tuple(Y.shape) != (B.m, k) or Y.stride(1) != 1:
+        raise ValueError("Y must be float64, m x k, unit column stride")
+    check(_lib.load().bcsr_spmm(B.m, B.n, B.a, B.b, B.nblocks, _ptr(B.browptr), _ptr(B.bcol), _ptr(B.bvals), k,
+                                _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), slots, _stream()), "bcsr_spmm")
+    return Y
+
+
 # ---------------------------------------------------------------- probes
 
 PROBE_KINDS = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "flush": 4, "gather_rows": 5,

@@ -76,3 +76,76 @@ def test_bcsr_edges_and_errors(spx, torch):
         spx.BCSR.from_csr(to_gpu(D), 3, 2)
     with pytest.raises(spx.SpxError):
         spx.bcsr_spmv(BD, torch.ones(8, dtype=torch.float64, device="cuda:0"), lanes=3)
+
+
+# ---------------------------------------------------------------- multi-vector product (a x 1 blocks)
+
+MM_KS = [1, 2, 3, 8, 16, 17, 32, 64, 65, 100]
+
+
+@pytest.mark.parametrize("a", [2, 4, 8])
+def test_bcsr_spmm_parity(spx, torch, mats, a):
+    """Y = A X through a x 1 dense blocks against the FP64 oracle (rel2 <= 1e-12
+    per column) for k from 1 to 100 (one and two column slabs, odd k, vector
+    and scalar X loads), every slot count, on ragged matrices."""
+    for name, A in mats.items():
+        B = spx.BCSR.from_csr(to_gpu(A), a, 1)
+        for k in MM_KS:
+            X = spgen.uniform(A.n * k, 27 + k).reshape(A.n, k)
+            ref = oracle.spmm(A, X)
+            Xd = torch.from_numpy(X).to("cuda:0")
+            kl = 1
+            while kl * (2 if k % 2 == 0 else 1) < min(k, 64 if k % 2 == 0 else 32):
+                kl <<= 1
+            for slots in sorted({0, 1, max(1, 64 // kl)}):
+                Y = spx.bcsr_spmm(B, Xd, slots=slots).cpu().numpy()
+                for j in range(k):
+                    assert oracle.rel2(Y[:, j], ref[:, j]) <= 1e-12, (name, a, k, slots, j)
+
+
+@pytest.mark.parametrize("a", [2, 4, 8])
+def test_bcsr_spmm_exact_and_strides(spx, torch, mats, a):
+    """Small-integer inputs: the oracle's sums exactly, also with padded row
+    strides (ldx, ldy > k), a misaligned X (scalar loads) and a stencil."""
+    for name in ("powerlaw", "stencil27"):
+        Ai = int_valued(mats[name], 28)
+        B = spx.BCSR.from_csr(to_gpu(Ai), a, 1)
+        for k in (4, 16, 24):
+            X = spgen.small_ints(Ai.n * k, 29).reshape(Ai.n, k)
+            ref = oracle.spmm(Ai, X)
+            Xd = torch.from_numpy(X).to("cuda:0")
+            assert np.array_equal(spx.bcsr_spmm(B, Xd).cpu().numpy(), ref), (name, a, k)
+            Xp = torch.zeros((Ai.n, k + 6), dtype=torch.float64, device="cuda:0")
+            Xp[:, :k] = Xd
+            Yp = torch.full((Ai.m, k + 2), 7.0, dtype=torch.float64, device="cuda:0")
+            spx.bcsr_spmm(B, Xp[:, :k], Y=Yp[:, :k])
+            assert np.array_equal(Yp[:, :k].cpu().numpy(), ref), (name, a, k, "ld")
+            assert bool((Yp[:, k:] == 7.0).all()), "columns past k untouched"
+            Xm = torch.zeros(Ai.n * k + 1, dtype=torch.float64, device="cuda:0")
+            Xm[1:] = Xd.reshape(-1)
+            Xmis = Xm[1:].view(Ai.n, k)
+            assert Xmis.data_ptr() % 16 != 0
+            assert np.array_equal(spx.bcsr_spmm(B, Xmis).cpu().numpy(), ref), (name, a, k, "misaligned")
+
+
+def test_bcsr_spmm_deterministic_and_errors(spx, torch, mats):
+    A = mats["stencil27"]
+    B = spx.BCSR.from_csr(to_gpu(A), 4, 1)
+    X = torch.from_numpy(spgen.uniform(A.n * 16, 30).reshape(A.n, 16)).to("cuda:0")
+    Y0 = spx.bcsr_spmm(B, X)
+    for _ in range(3):
+        assert torch.equal(spx.bcsr_spmm(B, X), Y0)
+    E = oracle.csr_from_coo(10, 7, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    BE = spx.BCSR.from_csr(to_gpu(E), 4, 1)
+    Y = spx.bcsr_spmm(BE, torch.ones((7, 5), dtype=torch.float64, device="cuda:0"))
+    assert np.array_equal(Y.cpu().numpy(), np.zeros((10, 5)))
+    with pytest.raises(spx.SpxError):   # only a x 1 blocks
+        spx.bcsr_spmm(spx.BCSR.from_csr(to_gpu(A), 4, 2), X)
+    with pytest.raises(spx.SpxError):   # a = 1 is the CSR product
+        spx.bcsr_spmm(spx.BCSR.from_csr(to_gpu(A), 1, 1), X)
+    with pytest.raises(ValueError):     # bitmap form
+        spx.bcsr_spmm(spx.BCSR.from_csr(to_gpu(A), 4, 1, True), X)
+    with pytest.raises(spx.SpxError):   # slots not a power of two
+        spx.bcsr_spmm(B, X, slots=3)
+    with pytest.raises(spx.SpxError):   # 16 slots x 8 lanes > 64
+        spx.bcsr_spmm(B, X, slots=16)
