@@ -559,12 +559,20 @@ def bcsr_spmm_rows(ctx, A):
         ref = Y.clone()
         tb = float(ctx["timer"].run([lambda: spx.spmm(A, X, Y=Y, plan=pb)], ctx["fsteps"], 3)[:, 0].mean())
         r = {"csr_us": t0 * 1e6, "csr_banded_us": tb * 1e6}
+        bw = spx.bandwidth(A)
         for a in (2, 4, 8):
             B = spx.BCSR.from_csr(A, a, 1)
             t = float(ctx["timer"].run([lambda: spx.bcsr_spmm(B, X, Y=Y)], ctx["fsteps"], 3)[:, 0].mean())
             r[f"bcsr_{a}x1"] = {"us": t * 1e6, "speedup_vs_csr": t0 / t, "gflops": 2 * A.nnz * k / t / 1e9,
                                 "density": A.nnz / (B.nblocks * a), "stored_bytes": B.stored_bytes(),
                                 "max_rel_diff_vs_csr": float((Y - ref).abs().max() / ref.abs().max())}
+            if a < 8:  # block rows swept band by band of the bandwidth
+                Yb = Y.clone()
+                tbb = float(ctx["timer"].run([lambda: spx.bcsr_spmm(B, X, Y=Y, row_period=bw)],
+                                             ctx["fsteps"], 3)[:, 0].mean())
+                r[f"bcsr_{a}x1"].update({"banded_us": tbb * 1e6, "banded_speedup_vs_csr": t0 / tbb,
+                                         "banded_equals_unbanded_bitwise": bool(torch.equal(Y, Yb))})
+                del Yb
             del B
             torch.cuda.empty_cache()
         res[f"k{k}"] = r

@@ -499,11 +499,15 @@ spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int32_t bitmap,
  * the block's explicit zeros.  X f64 n x k, row stride ldx >= k; Y f64 m x k,
  * row stride ldy >= k, overwritten.  `slots` blocks of a block row are
  * walked at a time (a power of two; 0 picks it from the mean blocks per
- * block row); k above 64 runs in column slabs.  Asynchronous on `stream`.
- * Other block shapes return SPX_ERR_UNSUPPORTED. */
+ * block row); k above 64 runs in column slabs.  row_period: 0, or P > 0 as
+ * in spx_plan_opts.row_period (rows; the bandwidth, csr_bandwidth): XCD j
+ * serves band j of every period of ceil(P / a) block rows, in ascending
+ * order, instead of the j-th eighth of the block rows; the same bits either
+ * way.  Asynchronous on `stream`.  Other block shapes return
+ * SPX_ERR_UNSUPPORTED. */
 spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int32_t nblocks, const int32_t *browptr,
                      const int32_t *bcol, const double *bvals, int32_t k, const double *X, int64_t ldx,
-                     double *Y, int64_t ldy, int32_t slots, void *stream);
+                     double *Y, int64_t ldy, int32_t slots, int32_t row_period, void *stream);
 
 /* ---------------------------------------------------------------- probes
  * Memory-system probes (the GPU counterparts of the paper's read / write

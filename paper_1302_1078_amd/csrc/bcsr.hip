@@ -15,6 +15,8 @@
 // blocks) lays lanes out as the CSR SpMM does, KL lanes x VEC columns per X
 // row and S slots walking a block row's blocks, and keeps a x VEC
 // accumulators per lane, so each X row gathered serves a rows of Y.
+#include <algorithm>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -294,7 +296,29 @@ struct BcsrMmArgs {
   int64_t ldx, ldy;
   int32_t m, mb, k;  // k: columns of this launch (a slab of at most KL x VEC)
   int32_t slots;     // S: slots per block row, S x KL <= 64
+  int32_t pb;        // 0, or a period of pb block rows: XCD j serves band j of every period
 };
+
+// Block row served by group g (in launch order) of workgroup b.  Without a
+// period: the j-th eighth of the block rows on XCD j (workgroup b runs on
+// XCD b mod 8).  With a period of pb block rows: XCD j serves band j,
+// R mod pb in [ceil(j pb / 8), ceil((j + 1) pb / 8)), in ascending order, so
+// the block rows that share X rows across neighbouring periods meet in one
+// L2 (the row period of the CSR plans, computed instead of listed).
+// Returns -1 past the end.
+__device__ __forceinline__ int64_t bcsr_block_row(const BcsrMmArgs& p, int64_t b, int64_t nb, int64_t g,
+                                                  int64_t groups_per_wg) {
+  if (p.pb <= 0) {
+    const int64_t R = static_cast<int64_t>(xcd_tile(static_cast<int>(b), static_cast<int>(nb))) * groups_per_wg + g;
+    return R < p.mb ? R : -1;
+  }
+  const int64_t j = b & 7, i = (b >> 3) * groups_per_wg + g;  // i-th block row of band j
+  const int64_t lo = (j * p.pb + 7) / 8, hi = ((j + 1) * p.pb + 7) / 8;
+  const int64_t w = hi - lo;
+  if (w <= 0) return -1;
+  const int64_t R = (i / w) * p.pb + lo + i % w;
+  return R < p.mb ? R : -1;
+}
 
 // Y[A R + r, :] = sum over the blocks q of block row R of bvals[A q + r] X[bcol[q], :].
 // Every round a slot takes U blocks (q, q + S, ...); the KL lanes of the
@@ -312,12 +336,11 @@ __global__ __launch_bounds__(kWG) void k_bcsr_spmm(const BcsrMmArgs p) {
   const int S = p.slots;
   const int G = S * KL;
   const int t = threadIdx.x, lane = t % kWave;
-  const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t R = (tile * kWG + t) / G;
+  const int64_t R = bcsr_block_row(p, blockIdx.x, gridDim.x, t / G, kWG / G);
   const int kl = lane % KL, slot = (lane % G) / KL;
   const int sbase = lane - kl;
   const int col = kl * VEC;
-  const bool active = R < p.mb;
+  const bool active = R >= 0;
   const bool colok = col < p.k;
   double acc[A][VEC];
 #pragma unroll
@@ -529,8 +552,9 @@ extern "C" spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int3
 extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int32_t nblocks,
                                 const int32_t* browptr, const int32_t* bcol, const double* bvals, int32_t k,
                                 const double* X, int64_t ldx, double* Y, int64_t ldy, int32_t slots,
-                                void* stream) {
-  if (m < 0 || n < 0 || nblocks < 0 || k < 0) return fail(SPX_ERR_INVALID, "bcsr_spmm: negative size");
+                                int32_t row_period, void* stream) {
+  if (m < 0 || n < 0 || nblocks < 0 || k < 0 || row_period < 0)
+    return fail(SPX_ERR_INVALID, "bcsr_spmm: negative size or period");
   if (b != 1 || (a != 2 && a != 4 && a != 8))
     return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: block %dx%d (a in {2, 4, 8}, b = 1, dense form)", a, b);
   if (m == 0 || k == 0) return SPX_OK;
@@ -561,10 +585,25 @@ extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int3
     }
     if ((S & (S - 1)) || S * kl > kWave)
       return fail(SPX_ERR_INVALID, "bcsr_spmm: slots=%d with %d lanes per X row (power of two, <= 64 lanes)", S, kl);
-    BcsrMmArgs p{browptr, bcol, bvals, X + c0, Y + c0, ldx, ldy, m, mb, kc, S};
-    const int64_t threads = static_cast<int64_t>(mb) * S * kl;
-    int64_t grid = (threads + kWG - 1) / kWG;
-    grid = (grid + 7) / 8 * 8;  // whole eighths: XCD j serves the j-th eighth of the block rows
+    // a period in block rows; one at least a block row beyond mb leaves the order ascending
+    const int64_t pb = row_period > 0 ? (row_period + a - 1) / a : 0;
+    BcsrMmArgs p{browptr, bcol, bvals, X + c0, Y + c0, ldx, ldy, m, mb, kc, S,
+                 (pb > 0 && pb < mb) ? static_cast<int32_t>(pb) : 0};
+    const int64_t per_wg = kWG / (S * kl);
+    int64_t grid;
+    if (p.pb > 0) {  // 8 x the workgroups of the largest band
+      int64_t most = 0;
+      for (int64_t j = 0; j < 8; ++j) {
+        const int64_t lo = (j * p.pb + 7) / 8, hi = ((j + 1) * p.pb + 7) / 8;
+        const int64_t rem = mb % p.pb;
+        const int64_t nj = (mb / p.pb) * (hi - lo) + std::max<int64_t>(0, std::min(hi, rem) - lo);
+        most = std::max(most, nj);
+      }
+      grid = 8 * ((most + per_wg - 1) / per_wg);
+    } else {
+      grid = (static_cast<int64_t>(mb) + per_wg - 1) / per_wg;
+      grid = (grid + 7) / 8 * 8;  // whole eighths: XCD j serves the j-th eighth of the block rows
+    }
     if (grid > 0x7fffffff) return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: grid too large");
     spx_status s = SPX_OK;
     if (a == 2) s = launch_bcsr_mm_a<2>(kl, vec, p, static_cast<unsigned>(grid), st);

@@ -620,9 +620,12 @@ def bcsr_spmv(B: BCSR, x: torch.Tensor, y: torch.Tensor | None = None, lanes: in
     return y
 
 
-def bcsr_spmm(B: BCSR, X: torch.Tensor, Y: torch.Tensor | None = None, slots: int = 0) -> torch.Tensor:
+def bcsr_spmm(B: BCSR, X: torch.Tensor, Y: torch.Tensor | None = None, slots: int = 0,
+              row_period: int = 0) -> torch.Tensor:
     """Y <- A X for a register-blocked A of a x 1 dense blocks (bcsr_spmm), FP64;
-    X n x k and Y m x k row-major (row strides taken from the tensors)."""
+    X n x k and Y m x k row-major (row strides taken from the tensors).
+    row_period: 0, or the rows of a period whose bands the XCDs sweep (the
+    matrix's bandwidth for a banded matrix; bitwise the same result)."""
     _dev(X)
     if X.dtype != torch.float64 or X.dim() != 2 or X.shape[0] != B.n or X.stride(1) != 1:
         raise ValueError("X must be float64, n x k, unit column stride")
@@ -634,7 +637,8 @@ def bcsr_spmm(B: BCSR, X: torch.Tensor, Y: torch.Tensor | None = None, slots: in
     if Y.dtype != torch.float64 or Y.dim() != 2 or tuple(Y.shape) != (B.m, k) or Y.stride(1) != 1:
         raise ValueError("Y must be float64, m x k, unit column stride")
     check(_lib.load().bcsr_spmm(B.m, B.n, B.a, B.b, B.nblocks, _ptr(B.browptr), _ptr(B.bcol), _ptr(B.bvals), k,
-                                _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), slots, _stream()), "bcsr_spmm")
+                                _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), slots, row_period, _stream()),
+          "bcsr_spmm")
     return Y
 
 

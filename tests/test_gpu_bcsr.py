@@ -149,3 +149,27 @@ def test_bcsr_spmm_deterministic_and_errors(spx, torch, mats):
         spx.bcsr_spmm(B, X, slots=3)
     with pytest.raises(spx.SpxError):   # 16 slots x 8 lanes > 64
         spx.bcsr_spmm(B, X, slots=16)
+
+
+@pytest.mark.parametrize("a", [2, 4, 8])
+def test_bcsr_spmm_row_period_bitwise(spx, torch, mats, a):
+    """Block rows swept band by band of a row period give the same bits as the
+    ascending order (each block row's sums are unchanged), for periods below,
+    at and above the number of rows."""
+    for name, A in mats.items():
+        G = to_gpu(A)
+        B = spx.BCSR.from_csr(G, a, 1)
+        bw = spx.bandwidth(G)
+        for k in (3, 16, 70):
+            X = torch.from_numpy(spgen.uniform(A.n * k, 32 + k).reshape(A.n, k)).to("cuda:0")
+            Y0 = spx.bcsr_spmm(B, X)
+            for P in (1, 3, 7, 100, max(bw, 1), A.m, 10 * A.m):
+                for slots in (0, 1):
+                    Y1 = spx.bcsr_spmm(B, X, slots=slots, row_period=P)
+                    if slots == 0:
+                        assert torch.equal(Y0.view(torch.uint8), Y1.view(torch.uint8)), (name, a, k, P)
+                    else:
+                        ref = oracle.spmm(A, X.cpu().numpy())
+                        assert oracle.rel2(Y1.cpu().numpy(), ref) <= 1e-12, (name, a, k, P, slots)
+    with pytest.raises(spx.SpxError):
+        spx.bcsr_spmm(B, X, row_period=-1)
