@@ -242,6 +242,10 @@ def bench_c2(ctx, A1=None):
     for name, A in mats:
         m, n, nnz = A.m, A.n, A.nnz
         rows = {}
+        # register-blocked alternative for the banded matrix's SpMM: 2 x 1
+        # blocks swept band by band of the bandwidth
+        Bst = spx.BCSR.from_csr(A, 2, 1) if name.startswith("stencil") else None
+        bw = spx.bandwidth(A) if Bst is not None else 0
         for k in (1, 8, 32):
             X64 = spgen.uniform(n * k, 7, spgen.TAG_X).reshape(n, k)
             Xq = spgen.to_f32(X64)
@@ -297,6 +301,16 @@ def bench_c2(ctx, A1=None):
                                         "equals_default_bitwise": bool(torch.equal(yb.view(torch.uint8),
                                                                                    yd.view(torch.uint8)))}
                     del pb, yb
+                    bv = Bst.bvals if vname == "f64" else Bst.bvals.to(vals.dtype)
+                    yc = torch.empty_like(yd)
+                    tc = float(ctx["timer"].run([lambda: spx.bcsr_spmm(Bst, Xd, Y=yc, row_period=bw, values=bv)],
+                                                ctx["fsteps"], 3)[:, 0].mean())
+                    r["bcsr_2x1_banded"] = {"us": tc * 1e6, "eff_gbs": b / tc / 1e9,
+                                            "frac_hbm": b / tc / 1e9 / PEAK_HBM_GBS,
+                                            "speedup_vs_default_plan": t / tc,
+                                            "max_rel_diff_vs_default_plan": float((yc.double() - yd.double()).abs().max()
+                                                                                  / yd.double().abs().max())}
+                    del bv, yc
                 if vname != "f64":
                     r["rel2_vs_gpu_fp64"] = max(rel2(yh[:, j], y3[:, j]) for j in range(k))
                     y5 = fp64_product(A.with_values(vals.double()), Xq64, k)
@@ -306,6 +320,7 @@ def bench_c2(ctx, A1=None):
                     base_t = t
                 rows[f"k{k}_{vname}"] = r
         out[name] = {"m": m, "nnz": nnz, "results": rows}
+        del Bst
     out["note"] = ("FP32/BF16 values with FP32 x/y and FP32 accumulation; rows longer than 256 use "
                    "compensated sums with an FP64 cross-lane reduction")
     return out

@@ -493,21 +493,26 @@ spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int32_t bitmap,
 
 /* Y <- A X with A in register-blocked form (Sec. 4.5) applied to the
  * multi-vector product (Sec. 5): dense a x 1 blocks (a in {2, 4, 8}, b = 1,
- * bitmap form not taken), FP64.  Each X row a block refers to is gathered
- * once and multiplied into a rows of Y, so a banded matrix whose consecutive
- * rows share columns gathers fewer X rows than through CSR, at the price of
- * the block's explicit zeros.  X f64 n x k, row stride ldx >= k; Y f64 m x k,
- * row stride ldy >= k, overwritten.  `slots` blocks of a block row are
- * walked at a time (a power of two; 0 picks it from the mean blocks per
- * block row); k above 64 runs in column slabs.  row_period: 0, or P > 0 as
- * in spx_plan_opts.row_period (rows; the bandwidth, csr_bandwidth): XCD j
- * serves band j of every period of ceil(P / a) block rows, in ascending
+ * bitmap form not taken).  Each X row a block refers to is gathered once and
+ * multiplied into a rows of Y, so a banded matrix whose consecutive rows
+ * share columns gathers fewer X rows than through CSR, at the price of the
+ * block's explicit zeros.  bvals holds the blocks' values as csr_to_bcsr
+ * lays them out, in vtype; (vtype, xytype) is (F64, F64) -- FP64 throughout
+ * -- or (F32 / BF16, F32): FP32 products and sums, without the compensated
+ * sums of the CSR kernels' long rows (blocked storage serves banded matrices,
+ * whose rows are short).  X n x k, row stride ldx >= k; Y m x k, row stride
+ * ldy >= k, overwritten.  `slots` blocks of a block row are walked at a time
+ * (a power of two; 0 picks it from the mean blocks per block row); k above
+ * 32 x (elements per 16 bytes) runs in column slabs.  row_period: 0, or
+ * P > 0 as in spx_plan_opts.row_period (rows; the bandwidth, csr_bandwidth):
+ * XCD j serves band j of every period of ceil(P / a) block rows, in ascending
  * order, instead of the j-th eighth of the block rows; the same bits either
- * way.  Asynchronous on `stream`.  Other block shapes return
+ * way.  Asynchronous on `stream`.  Other block shapes or type pairs return
  * SPX_ERR_UNSUPPORTED. */
 spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int32_t nblocks, const int32_t *browptr,
-                     const int32_t *bcol, const double *bvals, int32_t k, const double *X, int64_t ldx,
-                     double *Y, int64_t ldy, int32_t slots, int32_t row_period, void *stream);
+                     const int32_t *bcol, const void *bvals, spx_dtype vtype, int32_t k, const void *X,
+                     int64_t ldx, void *Y, int64_t ldy, spx_dtype xytype, int32_t slots, int32_t row_period,
+                     void *stream);
 
 /* ---------------------------------------------------------------- probes
  * Memory-system probes (the GPU counterparts of the paper's read / write

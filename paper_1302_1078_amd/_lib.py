@@ -134,8 +134,8 @@ SIGNATURES = {
     "csr_bcsr_count": (ctypes.c_int, [i32, i32, i32, P, P, i32, i32, P, P, ctypes.c_size_t, P]),
     "csr_to_bcsr": (ctypes.c_int, [i32, i32, i32, P, P, P, i32, i32, i32, P, P, P, P, P, P, ctypes.c_size_t, P]),
     "bcsr_spmv": (ctypes.c_int, [i32, i32, i32, i32, i32, i32, P, P, P, P, P, P, P, i32, P]),
-    "bcsr_spmm": (ctypes.c_int, [i32, i32, i32, i32, i32, P, P, P, i32, P, ctypes.c_int64, P, ctypes.c_int64,
-                                 i32, i32, P]),
+    "bcsr_spmm": (ctypes.c_int, [i32, i32, i32, i32, i32, P, P, P, ctypes.c_int, i32, P, ctypes.c_int64, P,
+                                 ctypes.c_int64, ctypes.c_int, i32, i32, P]),
     "spx_probe": (ctypes.c_int, [i32, P, P, ctypes.c_size_t, i32, P]),
     "spx_probe_index_gather": (ctypes.c_int, [P, i64, P, i32, i32, P, i32, P]),
     "spx_probe_chase": (ctypes.c_int, [P, i64, P, i64, P, P]),

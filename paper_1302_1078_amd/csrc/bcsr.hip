@@ -16,6 +16,7 @@
 // row and S slots walking a block row's blocks, and keeps a x VEC
 // accumulators per lane, so each X row gathered serves a rows of Y.
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -273,26 +274,38 @@ spx_status launch_bcsr(int a, int b, const BcsrArgs& p, unsigned grid, hipStream
 
 // ---------------------------------------------------------------- multi-vector product
 
-typedef double dbl2 __attribute__((ext_vector_type(2)));
+template <typename T, int N>
+struct VecOf {
+  typedef T type __attribute__((ext_vector_type(N)));
+};
 
-// VEC consecutive elements of an X row (16-byte aligned when VEC = 2)
-template <int VEC>
-__device__ __forceinline__ void ld_xrow(const double* q, double (&out)[VEC]) {
+// VEC consecutive elements of an X row (16-byte aligned when VEC > 1)
+template <typename T, int VEC>
+__device__ __forceinline__ void ld_xrow(const T* q, T (&out)[VEC]) {
   if constexpr (VEC == 1) {
     out[0] = *q;
   } else {
-    const dbl2 w = *reinterpret_cast<const dbl2*>(q);
-    out[0] = w[0];
-    out[1] = w[1];
+    const typename VecOf<T, VEC>::type w = *reinterpret_cast<const typename VecOf<T, VEC>::type*>(q);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) out[e] = w[e];
   }
+}
+
+// a block value as 32 bits for the cross-lane moves (BF16: its bits)
+__device__ __forceinline__ int32_t to_lane(float v) { return __float_as_int(v); }
+__device__ __forceinline__ int32_t to_lane(uint16_t v) { return static_cast<int32_t>(v); }
+template <typename VT>
+__device__ __forceinline__ float from_lane(int32_t v) {
+  if constexpr (std::is_same<VT, float>::value) return __int_as_float(v);
+  else return bf16_to_f32(static_cast<uint16_t>(v));
 }
 
 struct BcsrMmArgs {
   const int32_t* browptr;
   const int32_t* bcol;
-  const double* bvals;
-  const double* X;
-  double* Y;
+  const void* bvals;  // VT
+  const void* X;      // XT, offset to this launch's first column
+  void* Y;            // XT, likewise
   int64_t ldx, ldy;
   int32_t m, mb, k;  // k: columns of this launch (a slab of at most KL x VEC)
   int32_t slots;     // S: slots per block row, S x KL <= 64
@@ -328,9 +341,16 @@ __device__ __forceinline__ int64_t bcsr_block_row(const BcsrMmArgs& p, int64_t b
 // columns and values are loaded after this round's X gathers are issued:
 // loads complete in issue order, so waiting for the gathers does not wait
 // for them, and a round costs one memory round trip instead of two.
-template <int A, int KL, int VEC>
+template <typename VT, typename XT, int A, int KL, int VEC>
 __global__ __launch_bounds__(kWG) void k_bcsr_spmm(const BcsrMmArgs p) {
+  // FP64 values: FP64 throughout.  FP32 / BF16 values with FP32 X: FP32
+  // products and sums (no compensated sums: blocked storage serves banded
+  // matrices, whose rows are short)
   constexpr int U = (A >= 8) ? 2 : 4;
+  constexpr bool kF64 = std::is_same<VT, double>::value;
+  using Lane = typename std::conditional<kF64, double, int32_t>::type;  // a value as moved across lanes
+  const VT* bvals = static_cast<const VT*>(p.bvals);
+  const XT* X = static_cast<const XT*>(p.X);
   constexpr int PC = (U + KL - 1) / KL;      // block columns per lane
   constexpr int PV = (U * A + KL - 1) / KL;  // values per lane
   const int S = p.slots;
@@ -342,18 +362,18 @@ __global__ __launch_bounds__(kWG) void k_bcsr_spmm(const BcsrMmArgs p) {
   const int col = kl * VEC;
   const bool active = R >= 0;
   const bool colok = col < p.k;
-  double acc[A][VEC];
+  XT acc[A][VEC];
 #pragma unroll
   for (int r = 0; r < A; ++r)
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[r][e] = 0.0;
+    for (int e = 0; e < VEC; ++e) acc[r][e] = XT(0);
   int32_t q0 = 0, q1 = 0;
   if (active) {
     q0 = p.browptr[R];
     q1 = p.browptr[R + 1];
   }
   // block columns and values of the round starting at q (zero past q1)
-  auto fetch = [&](int32_t q, int32_t (&cl)[PC], double (&vl)[PV]) {
+  auto fetch = [&](int32_t q, int32_t (&cl)[PC], Lane (&vl)[PV]) {
 #pragma unroll
     for (int j = 0; j < PC; ++j) {
       const int u = kl + j * KL;
@@ -364,11 +384,15 @@ __global__ __launch_bounds__(kWG) void k_bcsr_spmm(const BcsrMmArgs p) {
     for (int j = 0; j < PV; ++j) {
       const int i = kl + j * KL, u = i / A, r = i % A;
       const int32_t qq = q + u * S;
-      vl[j] = (i < U * A && qq < q1) ? __builtin_nontemporal_load(p.bvals + static_cast<int64_t>(qq) * A + r) : 0.0;
+      if constexpr (kF64)
+        vl[j] = (i < U * A && qq < q1) ? __builtin_nontemporal_load(bvals + static_cast<int64_t>(qq) * A + r) : 0.0;
+      else
+        vl[j] = (i < U * A && qq < q1) ? to_lane(__builtin_nontemporal_load(bvals + static_cast<int64_t>(qq) * A + r))
+                                       : 0;
     }
   };
   int32_t clA[PC];
-  double vlA[PV];
+  Lane vlA[PV];
   const int32_t qs = q0 + slot;
   if (qs < q1) fetch(qs, clA, vlA);
   for (int32_t q = qs; q < q1; q += U * S) {
@@ -379,30 +403,34 @@ __global__ __launch_bounds__(kWG) void k_bcsr_spmm(const BcsrMmArgs p) {
       h[u] = q + u * S < q1;
       c[u] = __shfl(clA[u / KL], sbase + u % KL, kWave);
     }
-    double xv[U][VEC];
+    XT xv[U][VEC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (h[u] && colok) {
-        ld_xrow<VEC>(p.X + static_cast<int64_t>(c[u]) * p.ldx + col, xv[u]);
+        ld_xrow<XT, VEC>(X + static_cast<int64_t>(c[u]) * p.ldx + col, xv[u]);
       } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) xv[u][e] = 0.0;
+        for (int e = 0; e < VEC; ++e) xv[u][e] = XT(0);
       }
     }
     const bool more = q + U * S < q1;  // the same for the KL lanes of a slot
     int32_t clB[PC];
-    double vlB[PV];
+    Lane vlB[PV];
     if (more) fetch(q + U * S, clB, vlB);
-    double v[U * A];
+    XT v[U * A];
 #pragma unroll
-    for (int i = 0; i < U * A; ++i) v[i] = __shfl(vlA[i / KL], sbase + i % KL, kWave);
+    for (int i = 0; i < U * A; ++i) {
+      const Lane w = __shfl(vlA[i / KL], sbase + i % KL, kWave);
+      if constexpr (kF64) v[i] = w;
+      else v[i] = from_lane<VT>(w);
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int r = 0; r < A; ++r)
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
-          if (h[u]) acc[r][e] = __builtin_fma(v[u * A + r], xv[u][e], acc[r][e]);
+          if (h[u]) acc[r][e] = fma_t(v[u * A + r], xv[u][e], acc[r][e]);
     if (more) {
 #pragma unroll
       for (int j = 0; j < PC; ++j) clA[j] = clB[j];
@@ -421,32 +449,39 @@ __global__ __launch_bounds__(kWG) void k_bcsr_spmm(const BcsrMmArgs p) {
     for (int r = 0; r < A; ++r) {
       const int64_t row = R * A + r;
       if (row < p.m) {
-        double* y = p.Y + row * p.ldy + col;
+        XT* y = static_cast<XT*>(p.Y) + row * p.ldy + col;
         if constexpr (VEC == 1) {
           y[0] = acc[r][0];
         } else {
-          dbl2 w;
-          w[0] = acc[r][0];
-          w[1] = acc[r][1];
-          *reinterpret_cast<dbl2*>(y) = w;
+          typename VecOf<XT, VEC>::type w;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) w[e] = acc[r][e];
+          *reinterpret_cast<typename VecOf<XT, VEC>::type*>(y) = w;
         }
       }
     }
   }
 }
 
-template <int A>
+template <typename VT, typename XT, int A, int V>
 spx_status launch_bcsr_mm_a(int kl, int vec, const BcsrMmArgs& p, unsigned grid, hipStream_t st) {
-#define SPX_MMCASE(KL_, VEC_)                                    \
-  if (kl == KL_ && vec == VEC_) {                                \
-    k_bcsr_spmm<A, KL_, VEC_><<<grid, kWG, 0, st>>>(p);          \
-    SPX_LAUNCHED("k_bcsr_spmm");                                 \
-    return SPX_OK;                                               \
+#define SPX_MMCASE(KL_, VEC_)                                        \
+  if (kl == KL_ && vec == VEC_) {                                    \
+    k_bcsr_spmm<VT, XT, A, KL_, VEC_><<<grid, kWG, 0, st>>>(p);      \
+    SPX_LAUNCHED("k_bcsr_spmm");                                     \
+    return SPX_OK;                                                   \
   }
   SPX_MMCASE(1, 1) SPX_MMCASE(2, 1) SPX_MMCASE(4, 1) SPX_MMCASE(8, 1) SPX_MMCASE(16, 1) SPX_MMCASE(32, 1)
-  SPX_MMCASE(1, 2) SPX_MMCASE(2, 2) SPX_MMCASE(4, 2) SPX_MMCASE(8, 2) SPX_MMCASE(16, 2) SPX_MMCASE(32, 2)
+  SPX_MMCASE(1, V) SPX_MMCASE(2, V) SPX_MMCASE(4, V) SPX_MMCASE(8, V) SPX_MMCASE(16, V) SPX_MMCASE(32, V)
 #undef SPX_MMCASE
   return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: lanes %d x %d", kl, vec);
+}
+
+template <typename VT, typename XT, int V>
+spx_status launch_bcsr_mm_t(int a, int kl, int vec, const BcsrMmArgs& p, unsigned grid, hipStream_t st) {
+  if (a == 2) return launch_bcsr_mm_a<VT, XT, 2, V>(kl, vec, p, grid, st);
+  if (a == 4) return launch_bcsr_mm_a<VT, XT, 4, V>(kl, vec, p, grid, st);
+  return launch_bcsr_mm_a<VT, XT, 8, V>(kl, vec, p, grid, st);
 }
 
 }  // namespace
@@ -550,20 +585,25 @@ extern "C" spx_status bcsr_spmv(int32_t m, int32_t n, int32_t a, int32_t b, int3
 }
 
 extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int32_t nblocks,
-                                const int32_t* browptr, const int32_t* bcol, const double* bvals, int32_t k,
-                                const double* X, int64_t ldx, double* Y, int64_t ldy, int32_t slots,
-                                int32_t row_period, void* stream) {
+                                const int32_t* browptr, const int32_t* bcol, const void* bvals, spx_dtype vtype,
+                                int32_t k, const void* X, int64_t ldx, void* Y, int64_t ldy, spx_dtype xytype,
+                                int32_t slots, int32_t row_period, void* stream) {
   if (m < 0 || n < 0 || nblocks < 0 || k < 0 || row_period < 0)
     return fail(SPX_ERR_INVALID, "bcsr_spmm: negative size or period");
   if (b != 1 || (a != 2 && a != 4 && a != 8))
     return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: block %dx%d (a in {2, 4, 8}, b = 1, dense form)", a, b);
+  const bool f64 = vtype == SPX_F64 && xytype == SPX_F64;
+  if (!f64 && !((vtype == SPX_F32 || vtype == SPX_BF16) && xytype == SPX_F32))
+    return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: value / vector types (%d, %d)", vtype, xytype);
   if (m == 0 || k == 0) return SPX_OK;
   if (ldx < k || ldy < k) return fail(SPX_ERR_INVALID, "bcsr_spmm: ldx=%lld ldy=%lld < k=%d",
                                       static_cast<long long>(ldx), static_cast<long long>(ldy), k);
   if (!browptr || !Y || (nblocks > 0 && (!bcol || !bvals || !X))) return fail(SPX_ERR_INVALID, "bcsr_spmm: null pointer");
   const int32_t mb = (m + a - 1) / a;
+  const int V = f64 ? 2 : 4;  // elements per 16-byte X load
+  const size_t es = f64 ? 8 : 4;
   auto al16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
-  const int vec = (k % 2 == 0 && ldx % 2 == 0 && ldy % 2 == 0 && al16(X) && al16(Y)) ? 2 : 1;
+  const int vec = (k % V == 0 && ldx % V == 0 && ldy % V == 0 && al16(X) && al16(Y)) ? V : 1;
   const int width = 32 * vec;  // columns per launch
   hipStream_t st = as_stream(stream);
   for (int32_t c0 = 0; c0 < k; c0 += width) {
@@ -587,8 +627,8 @@ extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int3
       return fail(SPX_ERR_INVALID, "bcsr_spmm: slots=%d with %d lanes per X row (power of two, <= 64 lanes)", S, kl);
     // a period in block rows; one at least a block row beyond mb leaves the order ascending
     const int64_t pb = row_period > 0 ? (row_period + a - 1) / a : 0;
-    BcsrMmArgs p{browptr, bcol, bvals, X + c0, Y + c0, ldx, ldy, m, mb, kc, S,
-                 (pb > 0 && pb < mb) ? static_cast<int32_t>(pb) : 0};
+    BcsrMmArgs p{browptr, bcol, bvals, static_cast<const char*>(X) + c0 * es, static_cast<char*>(Y) + c0 * es,
+                 ldx, ldy, m, mb, kc, S, (pb > 0 && pb < mb) ? static_cast<int32_t>(pb) : 0};
     const int64_t per_wg = kWG / (S * kl);
     int64_t grid;
     if (p.pb > 0) {  // 8 x the workgroups of the largest band
@@ -605,10 +645,11 @@ extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int3
       grid = (grid + 7) / 8 * 8;  // whole eighths: XCD j serves the j-th eighth of the block rows
     }
     if (grid > 0x7fffffff) return fail(SPX_ERR_UNSUPPORTED, "bcsr_spmm: grid too large");
+    const unsigned g = static_cast<unsigned>(grid);
     spx_status s = SPX_OK;
-    if (a == 2) s = launch_bcsr_mm_a<2>(kl, vec, p, static_cast<unsigned>(grid), st);
-    else if (a == 4) s = launch_bcsr_mm_a<4>(kl, vec, p, static_cast<unsigned>(grid), st);
-    else s = launch_bcsr_mm_a<8>(kl, vec, p, static_cast<unsigned>(grid), st);
+    if (f64) s = launch_bcsr_mm_t<double, double, 2>(a, kl, vec, p, g, st);
+    else if (vtype == SPX_F32) s = launch_bcsr_mm_t<float, float, 4>(a, kl, vec, p, g, st);
+    else s = launch_bcsr_mm_t<uint16_t, float, 4>(a, kl, vec, p, g, st);
     if (s != SPX_OK) return s;
   }
   return SPX_OK;

@@ -621,24 +621,30 @@ def bcsr_spmv(B: BCSR, x: torch.Tensor, y: torch.Tensor | None = None, lanes: in
 
 
 def bcsr_spmm(B: BCSR, X: torch.Tensor, Y: torch.Tensor | None = None, slots: int = 0,
-              row_period: int = 0) -> torch.Tensor:
-    """Y <- A X for a register-blocked A of a x 1 dense blocks (bcsr_spmm), FP64;
-    X n x k and Y m x k row-major (row strides taken from the tensors).
-    row_period: 0, or the rows of a period whose bands the XCDs sweep (the
-    matrix's bandwidth for a banded matrix; bitwise the same result)."""
+              row_period: int = 0, values: torch.Tensor | None = None) -> torch.Tensor:
+    """Y <- A X for a register-blocked A of a x 1 dense blocks (bcsr_spmm); X n x k
+    and Y m x k row-major (row strides taken from the tensors).  values: the
+    blocks' values in another type (B.bvals converted to float32 or bfloat16,
+    with float32 X and Y); default B.bvals, FP64.  row_period: 0, or the rows of
+    a period whose bands the XCDs sweep (the matrix's bandwidth for a banded
+    matrix; bitwise the same result)."""
     _dev(X)
-    if X.dtype != torch.float64 or X.dim() != 2 or X.shape[0] != B.n or X.stride(1) != 1:
-        raise ValueError("X must be float64, n x k, unit column stride")
+    vals = B.bvals if values is None else values
+    if vals.numel() != B.bvals.numel():
+        raise ValueError("values must hold one entry per stored block value")
+    xt = torch.float64 if vals.dtype == torch.float64 else torch.float32
+    if X.dtype != xt or X.dim() != 2 or X.shape[0] != B.n or X.stride(1) != 1:
+        raise ValueError(f"X must be {xt}, n x k, unit column stride")
     if B.bitmap:
         raise ValueError("bcsr_spmm takes the dense block form")
     k = X.shape[1]
     if Y is None:
-        Y = torch.empty((B.m, k), dtype=torch.float64, device=X.device)
-    if Y.dtype != torch.float64 or Y.dim() != 2 or tuple(Y.shape) != (B.m, k) or Y.stride(1) != 1:
-        raise ValueError("Y must be float64, m x k, unit column stride")
-    check(_lib.load().bcsr_spmm(B.m, B.n, B.a, B.b, B.nblocks, _ptr(B.browptr), _ptr(B.bcol), _ptr(B.bvals), k,
-                                _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), slots, row_period, _stream()),
-          "bcsr_spmm")
+        Y = torch.empty((B.m, k), dtype=xt, device=X.device)
+    if Y.dtype != xt or Y.dim() != 2 or tuple(Y.shape) != (B.m, k) or Y.stride(1) != 1:
+        raise ValueError(f"Y must be {xt}, m x k, unit column stride")
+    check(_lib.load().bcsr_spmm(B.m, B.n, B.a, B.b, B.nblocks, _ptr(B.browptr), _ptr(B.bcol), _ptr(vals),
+                                dtype_code(vals), k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0), dtype_code(Y),
+                                slots, row_period, _stream()), "bcsr_spmm")
     return Y
 
 

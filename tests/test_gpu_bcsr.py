@@ -173,3 +173,37 @@ def test_bcsr_spmm_row_period_bitwise(spx, torch, mats, a):
                         assert oracle.rel2(Y1.cpu().numpy(), ref) <= 1e-12, (name, a, k, P, slots)
     with pytest.raises(spx.SpxError):
         spx.bcsr_spmm(B, X, row_period=-1)
+
+
+@pytest.mark.parametrize("vdtype", ["f32", "bf16"])
+@pytest.mark.parametrize("a", [2, 4])
+def test_bcsr_spmm_precision(spx, torch, mats, vdtype, a):
+    """FP32 / BF16 block values with FP32 X: every output within the FP32
+    bound gamma_(L+8) sum |a||x| of the FP64 oracle on the stored (quantised)
+    values; exact on small integers; the same bits with a row period."""
+    from _cases import check_bound, quantised
+    vt = torch.float32 if vdtype == "f32" else torch.bfloat16
+    for name, A in mats.items():
+        _, A5 = quantised(A, vdtype, torch)         # oracle matrix: the stored values, widened exactly
+        B = spx.BCSR.from_csr(to_gpu(A5), a, 1)
+        vals = B.bvals.to(vt)                        # exact: the values are representable
+        assert torch.equal(vals.double(), B.bvals)
+        L = A5.row_lengths()
+        for k in (3, 8, 16, 40):
+            Xq = spgen.to_f32(spgen.uniform(A.n * k, 33 + k).reshape(A.n, k))
+            Xd = torch.from_numpy(Xq).to("cuda:0")
+            Y5 = oracle.spmm(A5, Xq.astype(np.float64))
+            Y = spx.bcsr_spmm(B, Xd, values=vals)
+            Yh = Y.cpu().numpy()
+            for j in (0, k // 2, k - 1):
+                S = oracle.spmv_abs(A5, Xq[:, j].astype(np.float64))
+                check_bound(Yh[:, j], Y5[:, j], S, L, 1 << 30, (name, vdtype, a, k, j))
+            Yp = spx.bcsr_spmm(B, Xd, values=vals, row_period=max(spx.bandwidth(to_gpu(A5)), 1))
+            assert torch.equal(Y.view(torch.uint8), Yp.view(torch.uint8)), (name, vdtype, a, k)
+    Ai = int_valued(mats["stencil27"], 34)
+    Bi = spx.BCSR.from_csr(to_gpu(Ai), a, 1)
+    Xi = spgen.small_ints(Ai.n * 8, 35).reshape(Ai.n, 8)
+    Y = spx.bcsr_spmm(Bi, torch.from_numpy(Xi.astype(np.float32)).to("cuda:0"), values=Bi.bvals.to(vt))
+    assert np.array_equal(Y.double().cpu().numpy(), oracle.spmm(Ai, Xi))
+    with pytest.raises(ValueError):   # FP32 values take FP32 X
+        spx.bcsr_spmm(Bi, torch.from_numpy(Xi).to("cuda:0"), values=Bi.bvals.float())
