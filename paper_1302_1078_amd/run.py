@@ -37,6 +37,8 @@ def main(argv=None):
                     help="with --staged: the persistent double-buffered staged kernel")
     ap.add_argument("--banded", action="store_true",
                     help="rows ordered band by band of the matrix's bandwidth (plan row_period)")
+    ap.add_argument("--bcsr", type=int, default=0,
+                    help="SpMM through a x 1 register blocks (a = 2, 4 or 8; FP64), with --banded swept by band")
     ap.add_argument("--probe-copy-mib", type=int, default=0)
     ap.add_argument("--no-flush", action="store_true")
     ap.add_argument("--bandwidth", action="store_true",
@@ -104,6 +106,18 @@ def main(argv=None):
             ops.probe_index_gather(A.colind, x, gather=args.op == "xgather", blocks=4096)
         torch.cuda.synchronize()
         print(f"ran {args.op} on {args.workload} ({A.nnz} indices) x{args.reps}", flush=True)
+        return
+    if args.bcsr:
+        if k == 1 or args.dtype != "f64":
+            raise SystemExit("--bcsr serves the FP64 SpMM (k > 1)")
+        B = ops.BCSR.from_csr(A, args.bcsr, 1)
+        period = ops.bandwidth(A) if args.banded else 0
+        for _ in range(args.reps):
+            if flush is not None:
+                ops.probe("flush", flush)
+            ops.bcsr_spmm(B, X, Y=Y, row_period=period)
+        torch.cuda.synchronize()
+        print(f"ran bcsr_spmm {args.bcsr}x1 on {args.workload} ({B.nblocks} blocks, k={k}) x{args.reps}", flush=True)
         return
     plans = [ops.Plan.staged(A, k, xt, pipelined=args.pipelined) if args.staged
              else ops.Plan.for_matrix(A, ops.banded_opts(A, k, vt) if args.banded else ops.default_opts(k, vt))]
