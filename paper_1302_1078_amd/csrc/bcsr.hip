@@ -627,7 +627,9 @@ extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int3
       return fail(SPX_ERR_INVALID, "bcsr_spmm: slots=%d with %d lanes per X row (power of two, <= 64 lanes)", S, kl);
     // a period in block rows; one at least a block row beyond mb leaves the order ascending
     const int64_t pb = row_period > 0 ? (row_period + a - 1) / a : 0;
-    BcsrMmArgs p{browptr, bcol, bvals, static_cast<const char*>(X) + c0 * es, static_cast<char*>(Y) + c0 * es,
+    // X may be null when there are no blocks (it is never read then)
+    const void* Xc = X ? static_cast<const void*>(static_cast<const char*>(X) + c0 * es) : nullptr;
+    BcsrMmArgs p{browptr, bcol, bvals, Xc, static_cast<char*>(Y) + c0 * es,
                  ldx, ldy, m, mb, kc, S, (pb > 0 && pb < mb) ? static_cast<int32_t>(pb) : 0};
     const int64_t per_wg = kWG / (S * kl);
     int64_t grid;
