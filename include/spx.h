@@ -272,7 +272,8 @@ spx_status csr_transpose_index(int32_t m, int32_t n, int32_t nnz, const int32_t 
                                const int32_t *colind, int32_t *colptr, int32_t *rowind,
                                int32_t *perm, void *workspace, size_t ws_bytes, void *stream);
 
-/* dX <- A^T dY.  dY is m x k (lddy), dX is n x k (lddx), row-major.
+/* dX <- A^T dY.  dY is m x k (lddy), dX is n x k (lddx), row-major;
+ * lddy and lddx are at least k, also for k = 1 (SPX_ERR_INVALID otherwise).
  * mode 0 (CSC index, deterministic): needs colptr/rowind from
  * csr_transpose_index; every column is a gather in ascending row order, run
  * by the product kernels over the CSC pattern.  With perm (from the same

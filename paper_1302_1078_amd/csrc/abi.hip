@@ -181,7 +181,7 @@ extern "C" spx_status csr_spmv_t(int32_t m, int32_t n, int32_t nnz, const int32_
     if (s_nnz != SPX_OK) return s_nnz;
   }
   if (k < 1) return fail(SPX_ERR_INVALID, "csr_spmv_t: k=%d < 1", k);
-  if (k > 1 && (lddy < k || lddx < k)) return fail(SPX_ERR_INVALID, "csr_spmv_t: leading dims < k");
+  if (lddy < k || lddx < k) return fail(SPX_ERR_INVALID, "csr_spmv_t: leading dims < k");
   if (!pair_ok(vtype, xytype)) return fail(SPX_ERR_UNSUPPORTED, "csr_spmv_t: dtype pair");
   if (n > 0 && !dX) return fail(SPX_ERR_INVALID, "csr_spmv_t: dX is null");
   if (m > 0 && !rowptr) return fail(SPX_ERR_INVALID, "csr_spmv_t: rowptr is null");
@@ -196,8 +196,8 @@ extern "C" spx_status csr_spmv_t(int32_t m, int32_t n, int32_t nnz, const int32_
   a.values = values;
   a.X = dY;
   a.Y = dX;
-  a.ldx = (k == 1) ? 1 : lddy;
-  a.ldy = (k == 1) ? 1 : lddx;
+  a.ldx = lddy;
+  a.ldy = lddx;
   a.k = k;
   return launch_scatter_t(a, plan, m, n, nnz, vtype, xytype, as_stream(stream));
 }

@@ -24,8 +24,48 @@ enum { kScatterT = 0, kSddmm = 1, kSddmmSaved = 2 };
 // nonzero's arithmetic is the same expression whatever the batching.
 constexpr int kVisit = 4;
 
-template <typename VT, typename XT, int MODE>
-__device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_t p, int32_t p1, int step) {
+// Scatter-add merging (A^T dy with k = 1): a workgroup first adds its
+// contributions into an LDS table keyed by column (linear probing, a slot
+// claimed by compare-and-swap), then adds each occupied slot to dX with one
+// atomic.  On a power-law matrix the hottest columns take one atomic per
+// workgroup instead of one per nonzero, and contention on those addresses,
+// not the number of atomics, is what bounds the plain scatter.  A
+// contribution that finds no slot within kProbes goes straight to memory.
+constexpr int kMergeSlots = 2048;
+constexpr int kMergeBits = 11;
+constexpr int kProbes = 8;
+static_assert((1 << kMergeBits) == kMergeSlots, "slots a power of two");
+
+template <typename XT>
+struct MergeTab {
+  int32_t* key;  // column, or -1
+  XT* val;
+};
+
+template <typename XT>
+__device__ __forceinline__ void merge_add(const MergeTab<XT>& tb, XT* y, int64_t ldy, int32_t c, XT v) {
+  const uint32_t h = (static_cast<uint32_t>(c) * 2654435761u) >> (32 - kMergeBits);
+#pragma unroll
+  for (int q = 0; q < kProbes; ++q) {
+    const uint32_t sl = (h + q) & (kMergeSlots - 1);
+    int32_t k = tb.key[sl];
+    if (k == -1) {
+      k = atomicCAS(&tb.key[sl], -1, c);
+      if (k == -1) k = c;  // claimed
+    }
+    if (k == c) {  // an LDS add, kept apart from the global fallback below
+      auto* lv = reinterpret_cast<__attribute__((address_space(3))) XT*>(
+          reinterpret_cast<uintptr_t>(tb.val + sl) & 0xffffffffu);
+      __hip_atomic_fetch_add(lv, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
+    }
+  }
+  atomicAdd(y + static_cast<int64_t>(c) * ldy, v);
+}
+
+template <typename VT, typename XT, int MODE, bool MERGE = false>
+__device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_t p, int32_t p1, int step,
+                                          const MergeTab<XT>& tb = MergeTab<XT>{nullptr, nullptr}) {
   const XT* dy = static_cast<const XT*>(a.X) + static_cast<int64_t>(row) * a.ldx;
   const XT dy0 = (p < p1) ? dy[0] : XT(0);  // k = 1: one dY entry per row
   for (; p < p1; p += kVisit * step) {
@@ -45,7 +85,8 @@ __device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_
       for (int u = 0; u < kVisit; ++u) {
         if (!h[u]) continue;
         XT* dst = static_cast<XT*>(a.Y) + static_cast<int64_t>(c[u]) * a.ldy;
-        if (a.k == 1) atomicAdd(dst, v[u] * dy0);
+        if constexpr (MERGE) merge_add(tb, static_cast<XT*>(a.Y), a.ldy, c[u], v[u] * dy0);
+        else if (a.k == 1) atomicAdd(dst, v[u] * dy0);
         else
           for (int t = 0; t < a.k; ++t) atomicAdd(dst + t, v[u] * dy[t]);
       }
@@ -83,8 +124,9 @@ __device__ __forceinline__ void visit_run(const ProdArgs& a, int32_t row, int32_
 // consecutive nonzeros (coalesced index loads and output stores), the row of
 // each comes from a lockstep search over the rows' offsets in LDS, and the
 // rows' dY entries are staged in LDS once.
-template <typename VT, typename XT, int MODE>
-__device__ __forceinline__ void visit_stream(const ProdArgs& a, const BinDesc& d, int tile) {
+template <typename VT, typename XT, int MODE, bool MERGE = false>
+__device__ __forceinline__ void visit_stream(const ProdArgs& a, const BinDesc& d, int tile,
+                                             const MergeTab<XT>& tb = MergeTab<XT>{nullptr, nullptr}) {
   constexpr int kStreamRows = kWG;  // a stream tile: one bin row per thread (the bin table's layout)
   constexpr int kChunk = 1024, kPer = kChunk / kWG;
   __shared__ int32_t s_off[kStreamRows + 1];
@@ -157,7 +199,10 @@ __device__ __forceinline__ void visit_stream(const ProdArgs& a, const BinDesc& d
         v[u] = static_cast<XT>(ValueLoad<VT>::get(static_cast<const VT*>(a.values) + p[u]));
 #pragma unroll
       for (int u = 0; u < kPer; ++u)
-        if (ok[u]) atomicAdd(static_cast<XT*>(a.Y) + static_cast<int64_t>(c[u]) * a.ldy, v[u] * s_dy[lo[u]]);
+        if (ok[u]) {
+          if constexpr (MERGE) merge_add(tb, static_cast<XT*>(a.Y), a.ldy, c[u], v[u] * s_dy[lo[u]]);
+          else atomicAdd(static_cast<XT*>(a.Y) + static_cast<int64_t>(c[u]) * a.ldy, v[u] * s_dy[lo[u]]);
+        }
     } else {
       XT xr[kPer];
 #pragma unroll
@@ -228,6 +273,68 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
     if (rows[j] >= 0) visit_run<VT, XT, MODE>(a, rows[j], q0[j] + t % G, q1[j], G);
 }
 
+// A^T dy with k = 1 through the workgroup's merge table: the same traversal as
+// k_grad<kScatterT>, then one atomic per distinct column of the workgroup.
+template <typename VT, typename XT>
+__global__ __launch_bounds__(kWG) void k_scatter_merged(const ProdArgs a) {
+  __shared__ int32_t s_key[kMergeSlots];
+  __shared__ XT s_val[kMergeSlots];
+  const int b = blockIdx.x;
+  int bi = 0;
+  while (bi + 1 < a.nbins && b >= a.bins[bi + 1].blk_begin) ++bi;
+  const BinDesc d = a.bins[bi];
+  const int lb = b - d.blk_begin;
+  const int tile = (a.flags & SPX_FLAG_NO_XCD_MAP) ? lb : xcd_tile(lb, d.nblk);
+  const int t = threadIdx.x;
+  for (int i = t; i < kMergeSlots; i += kWG) {
+    s_key[i] = -1;
+    s_val[i] = XT(0);
+  }
+  __syncthreads();
+  const MergeTab<XT> tb{s_key, s_val};
+  if (d.lanes == 0) {  // one segment of a split row
+    if (tile < d.nrows) {
+      const int32_t sg = a.seg_row[tile];
+      const int32_t row = a.split_rows[sg];
+      const int32_t f = a.seg_first[sg];
+      const int32_t re = a.rowptr[row + 1];
+      const int32_t p0 = a.rowptr[row] + (tile - f) * a.chunk;
+      const int32_t p1 = min(p0 + a.chunk, re);
+      visit_run<VT, XT, kScatterT, true>(a, row, p0 + t, p1, kWG, tb);
+    }
+  } else if (d.lanes == SPX_LANES_STREAM) {
+    visit_stream<VT, XT, kScatterT, true>(a, d, tile, tb);
+  } else {
+    const int G = d.lanes;
+    const int rpg = d.rpg;
+    const int ng = kWG / G;
+    constexpr int kMaxRpg = 8;
+    int32_t rows[kMaxRpg], q0[kMaxRpg], q1[kMaxRpg];
+#pragma unroll
+    for (int j = 0; j < kMaxRpg; ++j) {
+      const int idx = (tile * rpg + j) * ng + t / G;
+      rows[j] = -1;
+      q0[j] = q1[j] = 0;
+      if (j < rpg && idx < d.nrows) rows[j] = a.row_perm ? a.row_perm[d.row_begin + idx] : d.row_begin + idx;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxRpg; ++j) {
+      if (rows[j] < 0) continue;
+      q0[j] = a.rowptr[rows[j]];
+      q1[j] = a.rowptr[rows[j] + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxRpg; ++j)
+      if (rows[j] >= 0) visit_run<VT, XT, kScatterT, true>(a, rows[j], q0[j] + t % G, q1[j], G, tb);
+  }
+  __syncthreads();
+  XT* y = static_cast<XT*>(a.Y);
+  for (int i = t; i < kMergeSlots; i += kWG) {
+    const int32_t c = s_key[i];
+    if (c >= 0) atomicAdd(y + static_cast<int64_t>(c) * a.ldy, s_val[i]);
+  }
+}
+
 template <typename XT>
 __global__ void k_zero_2d(XT* __restrict__ p, int64_t rows, int32_t k, int64_t ld) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -266,6 +373,14 @@ spx_status launch_scatter_t(ProdArgs& a, const spx_plan* plan, int32_t m, int32_
   for (int i = 0; i < a.nbins; ++i) grid = a.bins[i].blk_begin + a.bins[i].nblk;
   if (grid == 0) return SPX_OK;
   const unsigned g = static_cast<unsigned>(grid);
+  if (a.k == 1) {  // contributions merged per workgroup first
+    if (vt == SPX_F64 && xt == SPX_F64) k_scatter_merged<double, double><<<g, kWG, 0, st>>>(a);
+    else if (vt == SPX_F32 && xt == SPX_F32) k_scatter_merged<float, float><<<g, kWG, 0, st>>>(a);
+    else if (vt == SPX_BF16 && xt == SPX_F32) k_scatter_merged<uint16_t, float><<<g, kWG, 0, st>>>(a);
+    else return fail(SPX_ERR_UNSUPPORTED, "csr_spmv_t: unsupported dtype pair");
+    SPX_LAUNCHED("k_scatter_merged");
+    return SPX_OK;
+  }
   if (vt == SPX_F64 && xt == SPX_F64) k_grad<double, double, kScatterT><<<g, kWG, 0, st>>>(a);
   else if (vt == SPX_F32 && xt == SPX_F32) k_grad<float, float, kScatterT><<<g, kWG, 0, st>>>(a);
   else if (vt == SPX_BF16 && xt == SPX_F32) k_grad<uint16_t, float, kScatterT><<<g, kWG, 0, st>>>(a);

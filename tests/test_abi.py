@@ -68,6 +68,11 @@ def test_argument_errors_without_gpu(lib):
     assert lib.csr_spmm(4, 4, 0, null, null, null, 0, 8, null, 4, null, 8, 0, null, null) == _lib.SPX_ERR_INVALID
     assert lib.csr_spmv_t(4, 4, 1, null, null, null, null, null, null, 0, 1, null, 1, null, 1, 0, 0, null,
                           null) == _lib.SPX_ERR_INVALID
+    # leading dimensions below k are rejected for both modes, k = 1 included
+    for mode in (0, 1):
+        for lddy, lddx in ((0, 1), (1, 0)):
+            assert lib.csr_spmv_t(4, 4, 0, null, null, null, null, null, null, 0, 1, null, lddy, null, lddx, 0,
+                                  mode, null, null) == _lib.SPX_ERR_INVALID, (mode, lddy, lddx)
     assert lib.csr_from_coo_workspace_bytes(4, 4, -1, ctypes.byref(nb)) == _lib.SPX_ERR_INVALID
     assert lib.csr_from_coo(4, 4, 2, null, null, null, null, null, null, null, null, 0, null) == _lib.SPX_ERR_INVALID
     assert b"gfx950" in lib.spx_version()

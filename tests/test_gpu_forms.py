@@ -441,3 +441,70 @@ def test_saved_gather_graph_replay(spx, torch):
         torch.cuda.synchronize()
         assert torch.equal(y.view(torch.int64), y_ref.view(torch.int64)), r
         assert torch.equal(out.view(torch.int64), out_ref.view(torch.int64)), r
+
+
+def scatter_case(name: str) -> oracle.CSR:
+    """Patterns for the atomic transpose's per-workgroup merging: "hot" puts
+    most nonzeros in four columns, so every workgroup adds many contributions
+    into few table slots; "distinct" gives long rows of distinct columns, so a
+    workgroup meets more columns than its table holds and the rest go straight
+    to memory; "mixed" interleaves the two."""
+    rng = np.random.default_rng(sum(map(ord, name)))
+    if name == "hot":
+        m, n = 20000, 5000
+        L = rng.integers(1, 9, m)
+        cols = [np.unique(np.where(rng.random(l) < 0.8, rng.integers(0, 4, l), rng.integers(0, n, l)))
+                for l in L]
+    elif name == "distinct":
+        m, n = 6, 300_000
+        cols = [np.sort(rng.choice(n, 90_000, replace=False)) for _ in range(m)]
+    else:
+        m, n = 3000, 60_000
+        cols = []
+        for i in range(m):
+            l = int(rng.integers(0, 200)) if i % 3 else int(rng.integers(0, 6))
+            c = rng.integers(0, n, l)
+            c[: l // 4] = rng.integers(0, 8, l // 4)
+            cols.append(np.unique(c))
+    rowptr = np.zeros(m + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum([len(c) for c in cols])
+    colind = np.concatenate(cols).astype(np.int32)
+    return oracle.CSR(m, n, rowptr, colind, spgen.small_ints(len(colind), 3).astype(np.float64))
+
+
+@pytest.mark.parametrize("name", ["hot", "distinct", "mixed"])
+@pytest.mark.parametrize("vname", ["f64", "f32", "bf16"])
+def test_spmv_t_atomic_merging_exact(spx, torch, name, vname):
+    """Small-integer values and dy: every partial sum is exact in FP32 and
+    FP64, so the atomic scatter, in whatever order its additions land, gives
+    the oracle's A^T dy bit for bit, through its default traversal and a
+    stream-bin plan."""
+    A = scatter_case(name)
+    vt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[vname]
+    xt = torch.float64 if vname == "f64" else torch.float32
+    G = to_gpu(A, vt)
+    dy = spgen.small_ints(A.m, 4)
+    ref = oracle.spmv_t(A, dy)
+    assert np.abs(ref).max() < 2 ** 24
+    dyd = dev(torch, dy).to(xt)
+    for pl in (None, spx.Plan.for_matrix(G, keep_stream(spx.default_opts(1, vt)))):
+        got = spx.spmv_t(G, dyd, mode=1, plan=pl).double().cpu().numpy()
+        assert np.array_equal(got, ref), (name, vname)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_spmv_t_single_column_strided(spx, torch, mode):
+    """k = 1 given as m x 1 and n x 1 column views of wider arrays
+    (lddy = 3, lddx = 5): the result lands in the viewed column only, and
+    the other columns keep their contents."""
+    A = matrix("powerlaw", 38)
+    G = to_gpu(A)
+    dy = spgen.normal(A.m, 39)
+    ref = oracle.spmv_t(A, dy)
+    wide_dy = torch.zeros(A.m, 3, dtype=torch.float64, device="cuda:0")
+    wide_dy[:, 1] = dev(torch, dy)
+    wide_dx = torch.full((A.n, 5), 7.0, dtype=torch.float64, device="cuda:0")
+    spx.spmv_t(G, wide_dy[:, 1:2], mode=mode, out=wide_dx[:, 2:3])
+    got = wide_dx.cpu().numpy()
+    assert oracle.rel2(got[:, 2], ref) <= 1e-12
+    assert np.all(np.delete(got, 2, axis=1) == 7.0)
