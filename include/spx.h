@@ -325,8 +325,10 @@ spx_status csr_values_to_csc_noalloc(int32_t nnz, const int32_t *dest, const uin
 
 /* Sampled dot: out[p] = sum_t dY[row(p), t] * X[colind[p], t] for every
  * stored nonzero p (the gradient of y = A(values) x with respect to values).
- * dtype F64 or F32 for dY, X and out alike.  `plan` (nullable) is a plan of
- * the CSR pattern and only sets the traversal (rows by bins). */
+ * dtype F64 or F32 for dY, X and out alike.  dY is m x k (lddy) and X is
+ * n x k (ldx), row-major, with lddy and ldx at least k, also for k = 1
+ * (SPX_ERR_INVALID otherwise).  `plan` (nullable) is a plan of the CSR
+ * pattern and only sets the traversal (rows by bins). */
 spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t *rowptr, const int32_t *colind,
                      int32_t k, const void *dY, int64_t lddy, const void *X, int64_t ldx, void *out,
                      spx_dtype dtype, const spx_plan *plan, void *stream);

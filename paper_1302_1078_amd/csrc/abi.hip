@@ -212,7 +212,7 @@ extern "C" spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t
     if (s_nnz != SPX_OK) return s_nnz;
   }
   if (k < 1) return fail(SPX_ERR_INVALID, "csr_sddmm: k=%d < 1", k);
-  if (k > 1 && (lddy < k || ldx < k)) return fail(SPX_ERR_INVALID, "csr_sddmm: leading dims < k");
+  if (lddy < k || ldx < k) return fail(SPX_ERR_INVALID, "csr_sddmm: leading dims < k");
   if (dtype != SPX_F64 && dtype != SPX_F32)
     return fail(SPX_ERR_UNSUPPORTED, "csr_sddmm: dtype must be F64 or F32");
   if (m == 0 || nnz == 0) return SPX_OK;
@@ -225,9 +225,9 @@ extern "C" spx_status csr_sddmm(int32_t m, int32_t n, int32_t nnz, const int32_t
   a.rowptr = rowptr;
   a.colind = colind;
   a.X = dY;
-  a.ldx = (k == 1) ? 1 : lddy;
+  a.ldx = lddy;
   a.X2 = X;
-  a.ldx2 = (k == 1) ? 1 : ldx;
+  a.ldx2 = ldx;
   a.Y = out;
   a.k = k;
   return launch_sddmm(a, plan, m, nnz, dtype, false, as_stream(stream));

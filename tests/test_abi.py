@@ -73,6 +73,9 @@ def test_argument_errors_without_gpu(lib):
         for lddy, lddx in ((0, 1), (1, 0)):
             assert lib.csr_spmv_t(4, 4, 0, null, null, null, null, null, null, 0, 1, null, lddy, null, lddx, 0,
                                   mode, null, null) == _lib.SPX_ERR_INVALID, (mode, lddy, lddx)
+    for lddy, ldx in ((0, 1), (1, 0)):
+        assert lib.csr_sddmm(4, 4, 0, null, null, 1, null, lddy, null, ldx, null, 0, null,
+                             null) == _lib.SPX_ERR_INVALID, (lddy, ldx)
     assert lib.csr_from_coo_workspace_bytes(4, 4, -1, ctypes.byref(nb)) == _lib.SPX_ERR_INVALID
     assert lib.csr_from_coo(4, 4, 2, null, null, null, null, null, null, null, null, 0, null) == _lib.SPX_ERR_INVALID
     assert b"gfx950" in lib.spx_version()

@@ -508,3 +508,21 @@ def test_spmv_t_single_column_strided(spx, torch, mode):
     got = wide_dx.cpu().numpy()
     assert oracle.rel2(got[:, 2], ref) <= 1e-12
     assert np.all(np.delete(got, 2, axis=1) == 7.0)
+
+
+def test_sddmm_single_column_strided(spx, torch):
+    """k = 1 given as m x 1 and n x 1 column views of wider arrays
+    (lddy = 3, ldx = 4): the sampled dot reads the viewed columns only and
+    equals the vector call bit for bit (and the oracle within 1e-12)."""
+    A = matrix("powerlaw", 40)
+    G = to_gpu(A)
+    dy, x = spgen.normal(A.m, 41), spgen.uniform(A.n, 42)
+    wide_dy = torch.full((A.m, 3), 5.0, dtype=torch.float64, device="cuda:0")
+    wide_x = torch.full((A.n, 4), -3.0, dtype=torch.float64, device="cuda:0")
+    wide_dy[:, 2] = dev(torch, dy)
+    wide_x[:, 1] = dev(torch, x)
+    got = spx.sddmm(G, wide_dy[:, 2:3], wide_x[:, 1:2])
+    want = spx.sddmm(G, dev(torch, dy), dev(torch, x))
+    assert torch.equal(got, want)
+    ref = oracle.sddmm(A, dy.reshape(-1, 1), x.reshape(-1, 1))
+    assert oracle.rel2(got.cpu().numpy(), ref) <= 1e-12
