@@ -235,3 +235,27 @@ def test_c0(spx, torch):
     x = spgen.uniform(A.n, 5)
     y = spx.spmv(G, dev(torch, x), plan=spx.Plan.for_matrix(G)).cpu().numpy()
     check_f64(y, A, x, "C0 SpMV")
+
+
+@pytest.mark.parametrize("k", [8, 32])
+def test_c2_stencil_banded_and_blocked_spmm(spx, torch, c2_stencil, k):
+    """The two SpMM variants the benchmark reports beside the default on the
+    27-point stencil, in its launch configuration (FP64): the plan with a row
+    period equal to the bandwidth (bitwise the default plan's Y) and the 2 x 1
+    blocked SpMM in the same banded order, each against the oracle over every
+    element (per-row bound and rel2)."""
+    A, G = c2_stencil
+    X = spgen.uniform(A.n * k, 11, spgen.TAG_X).reshape(A.n, k)
+    Xd = dev(torch, X)
+    bw = spx.bandwidth(G)
+    assert bw == 128 * 128 + 128 + 1
+    Y0 = spx.spmm(G, Xd, plan=spx.Plan.for_matrix(G, spx.default_opts(k)))
+    Y1 = spx.spmm(G, Xd, plan=spx.Plan.for_matrix(G, spx.banded_opts(G, k)))
+    assert torch.equal(Y0, Y1)
+    del Y0
+    check_f64(Y1.cpu().numpy(), A, X, f"C2 27-point banded k={k}")
+    del Y1
+    B = spx.BCSR.from_csr(G, 2, 1)
+    Yb = spx.bcsr_spmm(B, Xd, row_period=bw).cpu().numpy()
+    del B
+    check_f64(Yb, A, X, f"C2 27-point 2x1 blocks banded k={k}")

@@ -1,6 +1,6 @@
 """Seeded random configurations against the oracle: plan options (bins,
 thresholds, lane widths, stream and split bins, split chunk, compensation
-threshold, flags), SpMM width, value type and matrix kind are drawn from a
+threshold, flags, row period), SpMM width, value type and matrix kind are drawn from a
 fixed seed per case, so every run checks the same combinations (60
 products, 24 backward cases, 8 batches).  Each
 product must meet the per-row error bound: FP64 2(L + 2) 2^-53 sum |a x|;
@@ -45,7 +45,8 @@ def random_opts(spx, rng, k):
         "nbins": nb, "upper": upper, "lanes": lanes,
         "split_chunk": int(rng.choice([256, 300, 1024, 4096])),
         "kahan_len": int(rng.choice([4, 64, 256, 100000])),
-        "max_k": k, "flags": flags})
+        "max_k": k, "flags": flags,
+        "row_period": int(rng.choice([0, 0, 0, 1, 7, 100, 5000]))})
 
 
 @pytest.mark.parametrize("case", range(60))
