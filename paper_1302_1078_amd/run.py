@@ -23,10 +23,12 @@ def main(argv=None):
                          "and then the same products launched one by one, --reps times each.  "
                          "locality: the locality sweep's matrices in turn (locality_matrices), --op "
                          "xgather / colstream / spmv --reps times on each")
-    ap.add_argument("--op", default="spmv", choices=["spmv", "spmm", "xgather", "colstream", "autograd"],
+    ap.add_argument("--op", default="spmv", choices=["spmv", "spmm", "xgather", "colstream", "autograd",
+                                                     "transpose_atomic"],
                     help="xgather / colstream: the index-gather probe over the matrix's colind "
                          "(with / without the x reads); autograd: forward + backward through the "
-                         "autograd Function (values and x both require gradients)")
+                         "autograd Function (values and x both require gradients); transpose_atomic: "
+                         "dx = A^T dy by the atomic scatter")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--reps", type=int, default=5)
@@ -97,6 +99,18 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(f"ran autograd forward + backward on {args.workload} ({A.nnz} nnz, {args.dtype}) x{args.reps}",
               flush=True)
+        return
+    if args.op == "transpose_atomic":
+        # dx = A^T dy by the atomic scatter (mode 1) through the CSR plan
+        plan = ops.Plan.for_matrix(A, ops.default_opts(1, vt))
+        dy = torch.from_numpy(spgen.normal(A.m, 1)).to(dev).to(xt)
+        dx = torch.empty(A.n, dtype=xt, device=dev)
+        for _ in range(args.reps):
+            if flush is not None:
+                ops.probe("flush", flush)
+            ops.spmv_t(A, dy, mode=1, plan=plan, out=dx)
+        torch.cuda.synchronize()
+        print(f"ran atomic transpose on {args.workload} ({A.nnz} nnz, {args.dtype}) x{args.reps}", flush=True)
         return
     if args.op in ("xgather", "colstream"):
         x = torch.from_numpy(spgen.uniform(A.n, 0)).to(dev)
