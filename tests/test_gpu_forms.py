@@ -526,3 +526,30 @@ def test_sddmm_single_column_strided(spx, torch):
     assert torch.equal(got, want)
     ref = oracle.sddmm(A, dy.reshape(-1, 1), x.reshape(-1, 1))
     assert oracle.rel2(got.cpu().numpy(), ref) <= 1e-12
+
+
+def test_spmv_t_atomic_graph_replay(spx, torch):
+    """The atomic transpose (zeroing kernel, then the merged scatter) captured
+    in a HIP graph and replayed four times with eager work between replays:
+    on small-integer inputs every replay gives the eager result exactly."""
+    A = scatter_case("mixed")
+    G = to_gpu(A, torch.float32)
+    plan = spx.Plan.for_matrix(G, spx.default_opts(1, torch.float32))
+    dy = dev(torch, spgen.small_ints(A.m, 6)).float()
+    eager = spx.spmv_t(G, dy, mode=1, plan=plan).clone()
+    assert np.array_equal(eager.double().cpu().numpy(), oracle.spmv_t(A, dy.double().cpu().numpy()))
+    out = torch.empty_like(eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        spx.spmv_t(G, dy, mode=1, plan=plan, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        spx.spmv_t(G, dy, mode=1, plan=plan, out=out)
+    for i in range(4):
+        out.fill_(float(i + 1))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), i
