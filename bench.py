@@ -63,8 +63,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the unflushed (warm) calls, so a kernel trace holds flushed calls only")
-    ap.add_argument("--forms", default="c0,c2,c3,c4",
-                    help="comma list of extra workloads (c0, c2, c3, c4; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep; rcm = RCM ordering; bcsr = register blocking; locality = column-locality sweep)")
+    ap.add_argument("--forms", default="c0,c2,c3,c4,shard",
+                    help="comma list of extra workloads (c0, c2, c3, c4; shard = one GPU's row block of an 8-GPU sharding; ksweep = SpMM k sweep and variants; occupancy = workgroups-per-CU sweep; rcm = RCM ordering; bcsr = register blocking; locality = column-locality sweep)")
     ap.add_argument("--form-steps", type=int, default=20)
     return ap.parse_args()
 
@@ -426,6 +426,100 @@ def bench_occupancy(ctx, A1=None):
 
 
 # ---------------------------------------------------------------- RCM ordering (Sec. 4.4)
+
+def row_shards(rowptr, parts: int):
+    """Row boundaries of `parts` contiguous row blocks holding about nnz/parts
+    nonzeros each: the 1D row-block partition balanced by nonzeros that a
+    multi-GPU SpMV / SpMM would use.  Block g is rows [cuts[g], cuts[g+1])."""
+    import numpy as np
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    m, nnz = len(rowptr) - 1, int(rowptr[-1])
+    cuts = [0]
+    for g in range(1, parts):
+        cuts.append(max(cuts[-1], min(m, int(np.searchsorted(rowptr, nnz * g // parts, side="left")))))
+    cuts.append(m)
+    return cuts
+
+
+def shard_of(torch, spx, A, r0, r1):
+    """Rows [r0, r1) of A as a CSR of their own (all n columns): row pointers
+    rebased, column indices and values as views into A's."""
+    p0, p1 = int(A.rowptr[r0]), int(A.rowptr[r1])
+    rp = (A.rowptr[r0:r1 + 1] - p0).contiguous()
+    return spx.CSR(rp, A.colind[p0:p1], A.values[p0:p1], (r1 - r0, A.n))
+
+
+XGMI_LINK_GBS = 153.0   # one xGMI link, per direction
+XGMI_LINKS = 7
+
+
+def bench_shard(ctx, A):
+    """One GPU's share of a row-block sharding over 8 GPUs, at its real shape:
+    the headline matrix cut into 8 row blocks balanced by nonzeros, and each
+    block's SpMV and SpMM (k = 16) timed against the full x and X, each call
+    flushed, again with warm caches, and through each shard's own autotuned
+    plans (flushed).  Reports every shard, the slowest one
+    against an eighth of the full product (the compute part of the scaling),
+    and the modelled allgather of x / X over 7 xGMI links (not measured: one
+    GPU)."""
+    import numpy as np
+    from paper_1302_1078_amd import autotune
+    torch, spx, dev = ctx["torch"], ctx["spx"], ctx["dev"]
+    x, X = ctx["c1_x"], ctx["c1_X"]
+    k = X.shape[1]
+    tv_full, tm_full = ctx["c1_times"]
+    parts = 8
+    rp = A.rowptr.cpu().numpy()
+    cuts = row_shards(rp, parts)
+    shards = []
+    for g in range(parts):
+        S = shard_of(torch, spx, A, cuts[g], cuts[g + 1])
+        pv = spx.Plan.for_matrix(S, spx.default_opts(1))
+        pm = spx.Plan.for_matrix(S, spx.default_opts(k))
+        y = torch.empty(S.m, dtype=torch.float64, device=dev)
+        Y = torch.empty((S.m, k), dtype=torch.float64, device=dev)
+        fns = [lambda: spx.spmv(S, x, y=y, plan=pv), lambda: spx.spmm(S, X, Y=Y, plan=pm)]
+        t = ctx["timer"].run(fns, ctx["fsteps"], 3).mean(axis=0)
+        tw = Timer(torch, dev, False).run(fns, ctx["fsteps"], 3).mean(axis=0)
+        # each shard's own tuned plans, as a sharded deployment would pick them
+        ov, _ = autotune.tune(S, x, batch=False)
+        om, _ = autotune.tune(S, X, batch=False)
+        tv_p, tm_p = spx.Plan.for_matrix(S, ov), spx.Plan.for_matrix(S, om)
+        tt = ctx["timer"].run([lambda: spx.spmv(S, x, y=y, plan=tv_p), lambda: spx.spmm(S, X, Y=Y, plan=tm_p)],
+                              ctx["fsteps"], 3).mean(axis=0)
+        lens = np.diff(rp[cuts[g]:cuts[g + 1] + 1])
+        shards.append({"rows": S.m, "nnz": S.nnz, "longest_row": int(lens.max()) if len(lens) else 0,
+                       "spmv_us": t[0] * 1e6, "spmm_us": t[1] * 1e6,
+                       "spmv_warm_us": tw[0] * 1e6, "spmm_warm_us": tw[1] * 1e6,
+                       "spmv_tuned_us": tt[0] * 1e6, "spmm_tuned_us": tt[1] * 1e6,
+                       "tuned_split_chunk": [ov.split_chunk, om.split_chunk]})
+        del S, pv, pm, y, Y, tv_p, tm_p
+    tv_max = max(r["spmv_us"] for r in shards)
+    tm_max = max(r["spmm_us"] for r in shards)
+    fw = Timer(torch, dev, False).run([lambda: spx.spmv(A, x, y=ctx["c1_y"], plan=ctx["c1_plans"][0]),
+                                       lambda: spx.spmm(A, X, Y=ctx["c1_Y"], plan=ctx["c1_plans"][1])],
+                                      ctx["fsteps"], 3).mean(axis=0) * 1e6
+    twv_max = max(r["spmv_warm_us"] for r in shards)
+    twm_max = max(r["spmm_warm_us"] for r in shards)
+    recv = (parts - 1) / parts
+    return {"workload": "power-law 1,048,576 x 1,048,576 (the headline matrix), 8 row blocks by nonzeros, FP64",
+            "parts": parts, "row_cuts": cuts, "shards": shards,
+            "full_spmv_us": tv_full * 1e6, "full_spmm_us": tm_full * 1e6,
+            "slowest_spmv_us": tv_max, "slowest_spmm_us": tm_max,
+            "compute_efficiency_spmv": tv_full * 1e6 / (parts * tv_max),
+            "compute_efficiency_spmm": tm_full * 1e6 / (parts * tm_max),
+            "tuned": {"slowest_spmv_us": max(r["spmv_tuned_us"] for r in shards),
+                      "slowest_spmm_us": max(r["spmm_tuned_us"] for r in shards),
+                      "compute_efficiency_spmv": tv_full * 1e6 / (parts * max(r["spmv_tuned_us"] for r in shards)),
+                      "compute_efficiency_spmm": tm_full * 1e6 / (parts * max(r["spmm_tuned_us"] for r in shards))},
+            "warm": {"full_spmv_us": float(fw[0]), "full_spmm_us": float(fw[1]),
+                     "slowest_spmv_us": twv_max, "slowest_spmm_us": twm_max,
+                     "compute_efficiency_spmv": float(fw[0]) / (parts * twv_max),
+                     "compute_efficiency_spmm": float(fw[1]) / (parts * twm_max)},
+            "modelled_allgather_x_us": 8 * A.n * recv / (XGMI_LINKS * XGMI_LINK_GBS * 1e9) * 1e6,
+            "modelled_allgather_X_us": 8 * A.n * k * recv / (XGMI_LINKS * XGMI_LINK_GBS * 1e9) * 1e6,
+            "note": "compute only; the allgather is modelled from the link rate, not measured (one GPU)"}
+
 
 def bench_rcm(ctx, A1=None):
     """Products before and after reverse Cuthill-McKee ordering (Sec. 4.4)
@@ -928,7 +1022,9 @@ def main():
 
     if not args.quick:
         ctx = {"torch": torch, "spx": spx, "spgen": spgen, "dev": dev, "timer": timer,
-               "fsteps": args.form_steps, "tmp": os.environ.get("TMPDIR", "/tmp")}
+               "fsteps": args.form_steps, "tmp": os.environ.get("TMPDIR", "/tmp"),
+               "c1_x": x, "c1_X": X, "c1_y": y, "c1_Y": Y, "c1_plans": (plan_v, plan_m),
+               "c1_times": (float(tv.mean()), float(tm.mean()))}
         forms = {}
         for name in [f.strip() for f in args.forms.split(",") if f.strip()]:
             f0 = time.time()
@@ -951,6 +1047,8 @@ def main():
                     forms[name] = bench_bcsr(ctx, A)
                 elif name == "locality":
                     forms[name] = bench_locality(ctx, A)
+                elif name == "shard":
+                    forms[name] = bench_shard(ctx, A)
                 forms[name]["bench_s"] = round(time.time() - f0, 1)
             except Exception as e:  # a failing form is reported, not hidden
                 forms[name] = {"error": repr(e)}

@@ -103,3 +103,31 @@ def test_cpu_baseline_protocol_small():
         assert r["spmv_gflops"] > 0 and r["spmm_gflops"] > 0
     one = out["one_thread"]
     assert abs(one["gflops"] - (2000 + 8000) / (one["spmv_ms"] + one["spmm_ms"]) / 1e6) < 1e-9 * one["gflops"]
+
+
+def test_row_shards_balance_by_nonzeros():
+    """The row-block partition: contiguous blocks covering every row once, each
+    within one row's length of nnz/parts (a block boundary can only fall
+    between rows), and degenerate inputs (fewer rows than parts, no
+    nonzeros, one dominating row) still give parts + 1 ordered cuts."""
+    import numpy as np
+    rng = np.random.default_rng(3)
+    for m, parts in ((1000, 8), (37, 8), (5, 8), (1, 8), (20000, 3)):
+        L = rng.integers(0, 50, m)
+        L[rng.integers(0, m)] = 5000   # one long row
+        rowptr = np.concatenate([[0], np.cumsum(L)])
+        cuts = bench.row_shards(rowptr, parts)
+        assert len(cuts) == parts + 1 and cuts[0] == 0 and cuts[-1] == m
+        assert all(a <= b for a, b in zip(cuts, cuts[1:]))
+        nnz = int(rowptr[-1])
+        for g in range(parts):
+            # each cut is the first row boundary at or past g * nnz / parts
+            if 0 < g:
+                c = cuts[g]
+                target = nnz * g // parts
+                assert rowptr[c] >= target or c == m
+                assert c == 0 or rowptr[c - 1] < target or cuts[g - 1] == c
+        per = [int(rowptr[cuts[g + 1]] - rowptr[cuts[g]]) for g in range(parts)]
+        assert sum(per) == nnz
+        assert max(per) <= nnz / parts + L.max() + 1
+    assert bench.row_shards(np.zeros(11, dtype=np.int64), 4) == [0, 0, 0, 0, 10]

@@ -259,3 +259,24 @@ def test_c2_stencil_banded_and_blocked_spmm(spx, torch, c2_stencil, k):
     Yb = spx.bcsr_spmm(B, Xd, row_period=bw).cpu().numpy()
     del B
     check_f64(Yb, A, X, f"C2 27-point 2x1 blocks banded k={k}")
+
+
+def test_c1_row_shards(spx, torch, c1_matrix):
+    """The headline matrix cut into the 8 row blocks balanced by nonzeros that
+    the benchmark's shard form times: each block's SpMV and SpMM (k = 16)
+    through its own default plan, against the full x and X; the blocks'
+    results stacked are checked against the oracle over every element."""
+    import bench
+    A, G = c1_matrix
+    cuts = bench.row_shards(A.rowptr, 8)
+    x = spgen.uniform(A.n, 1)
+    k = 16
+    X = spgen.uniform(A.n * k, 2).reshape(A.n, k)
+    xd, Xd = dev(torch, x), dev(torch, X)
+    ys, Ys = [], []
+    for g in range(8):
+        S = bench.shard_of(torch, spx, G, cuts[g], cuts[g + 1])
+        ys.append(spx.spmv(S, xd, plan=spx.Plan.for_matrix(S, spx.default_opts(1))).cpu().numpy())
+        Ys.append(spx.spmm(S, Xd, plan=spx.Plan.for_matrix(S, spx.default_opts(k))).cpu().numpy())
+    check_f64(np.concatenate(ys), A, x, "C1 SpMV, 8 row blocks")
+    check_f64(np.concatenate(Ys), A, X, "C1 SpMM k=16, 8 row blocks")
