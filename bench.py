@@ -781,13 +781,20 @@ def bench_c4(ctx):
     import tempfile
     cache = os.path.join(tempfile.mkdtemp(prefix="spx_tune_"), "autotune_c4.json")  # tune afresh
     t1 = time.time()
-    opts = [autotune.tune(A, X, reps=3, cache_path=cache)[0] for A, X in zip(mats32, X32)]
+    opts, tune_report = autotune.tune_batch(mats32, X32, reps=3, cache_path=cache)
     tune_s = time.time() - t1
     B = Batched(mats32, X32, opts=opts)
     g = B.capture()
     t_graph = float(ctx["timer"].run([g.replay], ctx["fsteps"], 3)[:, 0].mean())
     t_run = float(ctx["timer"].run([B.run], ctx["fsteps"], 3)[:, 0].mean())
-    plans32 = [spx.Plan.for_matrix(A, o) for A, o in zip(mats32, opts)]
+    # the same batch with every matrix on its default plan, for comparison
+    Bd = Batched(mats32, X32)
+    gd = Bd.capture()
+    t_graph_default = float(ctx["timer"].run([gd.replay], ctx["fsteps"], 3)[:, 0].mean())
+    del gd, Bd
+    # sequential single calls get plans tuned for single calls
+    single = [autotune.tune(A, X, reps=3, batch=False)[0] for A, X in zip(mats32, X32)]
+    plans32 = [spx.Plan.for_matrix(A, o) for A, o in zip(mats32, single)]
     plans64 = [spx.Plan.for_matrix(A, spx.default_opts(k)) for A, k in zip(mats64, ks)]
     outs32 = [torch.empty_like(Y) for Y in B.Ys]
     outs64 = [torch.empty(Y.shape, dtype=torch.float64, device=dev) for Y in B.Ys]
@@ -819,7 +826,8 @@ def bench_c4(ctx):
                         "log-uniform [1e3, 2e5], FP32 values, k in {1, 4, 16}",
             "matrices": len(specs), "total_nnz": int(sum(A.nnz for A in mats32)),
             "total_rows": int(sum(A.m for A in mats32)), "tiles": info["tiles"], "grid": info["grid"],
-            "graph_us": t_graph * 1e6, "run_us": t_run * 1e6, "seq_f32_us": t_seq32 * 1e6,
+            "graph_us": t_graph * 1e6, "run_us": t_run * 1e6, "graph_default_plans_us": t_graph_default * 1e6,
+            "autotune": tune_report, "seq_f32_us": t_seq32 * 1e6,
             "seq_f64_us": t_seq64 * 1e6, "gflops_graph": flops / t_graph / 1e9,
             "eff_gbs_graph": bytes32 / t_graph / 1e9,
             "speedup_vs_seq_f32": t_seq32 / t_graph, "speedup_vs_seq_f64": t_seq64 / t_graph,

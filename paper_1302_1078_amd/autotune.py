@@ -28,7 +28,7 @@ from .ops import CSR, Plan, bandwidth, default_opts, spmm, spmv
 STREAM = 512  # SPX_LANES_STREAM
 
 
-TUNER_VERSION = 3  # part of the cache key: decisions of other tuner versions are not reused
+TUNER_VERSION = 4  # part of the cache key: decisions of other tuner versions are not reused
 
 
 def structure_key(A: CSR, k: int, setting: str = "") -> str:
@@ -133,10 +133,40 @@ def time_opts(A: CSR, X: torch.Tensor, opts: PlanOpts, reps: int = 5, calls: int
     return ms[len(ms) // 2]
 
 
+def time_in_batch(A: CSR, X: torch.Tensor, opts: PlanOpts, reps: int = 5, calls: int = 8,
+                  fill_tiles: int = 4096, max_copies: int = 64) -> float:
+    """Time per copy (ms) of `opts` inside a batch that fills the chip: the
+    matrix alone when its tiles already do, otherwise enough copies of it
+    (same A and X, separate outputs) to reach about `fill_tiles` tiles.  In
+    a batch of many matrices the grid is full, so what a plan costs there is
+    its throughput, not the latency of its own few tiles; timing a small
+    matrix alone would reward plans that only add parallelism."""
+    from .batch import Batched
+    one = Batched([A], [X], opts=[opts])
+    tiles = max(1, one.info()["tiles"])
+    copies = max(1, min(max_copies, -(-fill_tiles // tiles)))
+    B = one if copies == 1 else Batched([A] * copies, [X] * copies, opts=[opts] * copies)
+    B.run()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(calls):
+            B.run()
+        e1.record()
+        ts.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) / calls for a, b in ts)
+    return ms[len(ms) // 2] / copies
+
+
 def tune(A: CSR, X: torch.Tensor, reps: int = 5, cache_path: str | None = None,
          cands: list | None = None, batch: bool = True, margin: float = 0.05) -> tuple:
     """Return (best PlanOpts, report dict).  X is x (1-D) or X (n x k).  The
-    first candidate is the baseline that another must beat by `margin`."""
+    first candidate is the baseline that another must beat by `margin`.
+    With batch=True each candidate is timed as the batch runs it, inside a
+    batch that fills the chip (time_in_batch); otherwise as a single
+    product (time_opts)."""
     k = 1 if X.dim() == 1 else X.shape[1]
     key = structure_key(A, k, f"batch={int(batch)}:margin={margin}")
     cache = load_cache(cache_path)
@@ -158,7 +188,7 @@ def tune(A: CSR, X: torch.Tensor, reps: int = 5, cache_path: str | None = None,
         if batch:
             c.flags |= SPX_FLAG_KEEP_STREAM
         timed.append(c)
-    times = [time_opts(A, X, o, reps) for o in timed]
+    times = [time_in_batch(A, X, o, reps) if batch else time_opts(A, X, o, reps) for o in timed]
     best = min(range(len(cands)), key=lambda i: times[i])
     if times[best] > times[0] * (1.0 - margin):
         best = 0
@@ -170,3 +200,58 @@ def tune(A: CSR, X: torch.Tensor, reps: int = 5, cache_path: str | None = None,
             json.dump(cache, f)
         os.replace(tmp, cache_path)
     return cands[best], report
+
+
+def time_batch(mats: list, Xs: list, opts: list, reps: int = 5, calls: int = 4) -> float:
+    """Median time (ms) of one run of the whole batch with these options,
+    over `reps` samples of `calls` back-to-back runs."""
+    from .batch import Batched
+    B = Batched(mats, Xs, opts=opts)
+    B.run()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(calls):
+            B.run()
+        e1.record()
+        ts.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) / calls for a, b in ts)
+    return ms[len(ms) // 2]
+
+
+def tune_batch(mats: list, Xs: list, reps: int = 3, margin: float = 0.01, rounds: int = 3,
+               cache_path: str | None = None) -> tuple:
+    """Plan options for a batch: each matrix's own choice (tune with
+    batch=True), accepted for a group of matrices only if the whole batch
+    gets faster with it.  A group is the matrices of one SpMM width (they
+    share a launch).  Per-matrix timings cannot see how the choices combine
+    in one launch ordered heaviest tile first (a plan with fewer, heavier
+    tiles can lengthen the launch's tail), so every group's change is
+    checked on the batch as it runs: the current and the trial options are
+    timed alternately `rounds` times, and the trial is kept only if its
+    median is faster by `margin`.  Returns (options per matrix, report)."""
+    ks = [1 if X.dim() == 1 else X.shape[1] for X in Xs]
+    picks = [tune(A, X, reps=reps, cache_path=cache_path)[0] for A, X in zip(mats, Xs)]
+    chosen = [default_opts(k, A.values.dtype) for A, k in zip(mats, ks)]
+    report = {"changed_per_matrix": sum(p.to_dict() != c.to_dict() for p, c in zip(picks, chosen)), "groups": {}}
+    for kk in sorted(set(ks)):
+        idx = [i for i, k in enumerate(ks) if k == kk and picks[i].to_dict() != chosen[i].to_dict()]
+        if not idx:
+            continue
+        trial = list(chosen)
+        for i in idx:
+            trial[i] = picks[i]
+        cur_t, new_t = [], []
+        for _ in range(rounds):
+            cur_t.append(time_batch(mats, Xs, chosen))
+            new_t.append(time_batch(mats, Xs, trial))
+        cur, new = sorted(cur_t)[rounds // 2], sorted(new_t)[rounds // 2]
+        keep = new < cur * (1.0 - margin)
+        report["groups"][kk] = {"matrices_changed": len(idx), "batch_ms": cur, "trial_ms": new, "accepted": keep}
+        if keep:
+            chosen = trial
+    report["accepted_matrices"] = sum(c.to_dict() != default_opts(k, A.values.dtype).to_dict()
+                                      for A, k, c in zip(mats, ks, chosen))
+    return chosen, report

@@ -1,8 +1,8 @@
 """Host logic of the autotuner, with the GPU timing replaced by fixed times:
 the default plan (first candidate) is kept unless another is faster by the
-margin; with batch=True candidates are timed with stream bins kept as tiles
-but returned without that flag; decisions are cached under a key that
-carries the tuner's settings."""
+margin; with batch=True candidates are timed inside a batch, with stream
+bins kept as tiles, and returned without that flag; decisions are cached
+under a key that carries the tuner's settings."""
 import json
 from types import SimpleNamespace
 
@@ -28,6 +28,7 @@ def run_tune(monkeypatch, A, rel_times, **kw):
         return 1.0 * rel_times[i] if i < len(rel_times) else 1.0
 
     monkeypatch.setattr(autotune, "time_opts", fake_time)
+    monkeypatch.setattr(autotune, "time_in_batch", fake_time)
     x = torch.ones(3, dtype=torch.float64)
     best, rep = autotune.tune(A, x, **kw)
     return best, rep, seen
@@ -79,6 +80,7 @@ def test_banded_candidate_for_single_spmm(monkeypatch, fake_matrix):
     from paper_1302_1078_amd import autotune
     seen = []
     monkeypatch.setattr(autotune, "time_opts", lambda A_, X_, o, reps=5, calls=8: seen.append(o) or 1.0)
+    monkeypatch.setattr(autotune, "time_in_batch", lambda A_, X_, o, reps=5, calls=8: seen.append(o) or 1.0)
     monkeypatch.setattr(autotune, "bandwidth", lambda A_: 1)
     X = torch.ones((3, 4), dtype=torch.float64)
     n = len(autotune.candidates(4))
@@ -94,3 +96,58 @@ def test_banded_candidate_for_single_spmm(monkeypatch, fake_matrix):
     monkeypatch.setattr(autotune, "bandwidth", lambda A_: 3)   # >= m: ascending anyway
     autotune.tune(fake_matrix, X, batch=False)
     assert len(seen) == n
+
+
+def test_batch_and_single_timing_paths(monkeypatch, fake_matrix):
+    """batch=True times candidates inside a batch (time_in_batch), batch=False
+    as single products (time_opts); neither calls the other."""
+    from paper_1302_1078_amd import autotune
+    calls = {"batch": 0, "single": 0}
+
+    def tb(A_, X_, o, reps=5, calls_=8):
+        calls["batch"] += 1
+        return 1.0
+
+    def ts(A_, X_, o, reps=5, calls_=8):
+        calls["single"] += 1
+        return 1.0
+
+    monkeypatch.setattr(autotune, "time_in_batch", tb)
+    monkeypatch.setattr(autotune, "time_opts", ts)
+    x = torch.ones(3, dtype=torch.float64)
+    autotune.tune(fake_matrix, x, batch=True)
+    assert calls["batch"] == len(autotune.candidates(1)) and calls["single"] == 0
+    autotune.tune(fake_matrix, x, batch=False)
+    assert calls["single"] == len(autotune.candidates(1))
+
+
+def test_tune_batch_accepts_a_group_only_if_the_batch_gets_faster(monkeypatch):
+    """Per-matrix picks are kept per SpMM width only when the whole batch's
+    time drops by the margin; otherwise that group keeps its defaults."""
+    from paper_1302_1078_amd import autotune
+    from paper_1302_1078_amd._lib import PlanOpts
+    mats = [SimpleNamespace(m=3, n=3, nnz=5, values=torch.ones(5, dtype=torch.float32)) for _ in range(4)]
+    Xs = [torch.ones(3), torch.ones(3, 4), torch.ones(3), torch.ones(3, 4)]
+
+    def pick(A, X, reps=3, cache_path=None):
+        k = 1 if X.dim() == 1 else X.shape[1]
+        d = autotune.default_opts(k, torch.float32).to_dict()
+        d["split_chunk"] = 1024
+        return PlanOpts.from_dict(d), {}
+
+    monkeypatch.setattr(autotune, "tune", pick)
+
+    def fake_batch(ms, xs, opts, reps=5, calls=4):
+        # the k = 1 picks make the batch 10 % faster, the k = 4 picks 10 % slower
+        t = 1.0
+        for X, o in zip(xs, opts):
+            if o.split_chunk == 1024:
+                t *= 0.95 if X.dim() == 1 else 1.05
+        return t
+
+    monkeypatch.setattr(autotune, "time_batch", fake_batch)
+    chosen, rep = autotune.tune_batch(mats, Xs)
+    assert [o.split_chunk for o in chosen] == [1024, autotune.default_opts(4).split_chunk,
+                                               1024, autotune.default_opts(4).split_chunk]
+    assert rep["groups"][1]["accepted"] and not rep["groups"][4]["accepted"]
+    assert rep["changed_per_matrix"] == 4 and rep["accepted_matrices"] == 2

@@ -11,7 +11,8 @@ assembled by the oracle itself; nothing it reads comes from the GPU.
       through the staged plan the benchmark reports beside the default.
   C3  power-law 524,288 rows, FP32: one autograd forward and backward
       (y, dx = A^T dy, dvalues).
-  C4  the 256-matrix batch with autotuned plans, replayed from a HIP graph.
+  C4  the 256-matrix batch with autotuned plans (autotune.tune_batch), replayed
+      from a HIP graph.
   C0  uniform 10,000 rows: SpMV.
 
 FP64 results: every row within 2(L + 2) 2^-53 sum_p |a_p x_p| and rel2 <=
@@ -212,7 +213,8 @@ def test_c4_batch(spx, torch):
         mats.append(G.with_values(G.values.float()))
         Xs.append(dev(torch, X[:, 0] if s.k == 1 else X))
         refs.append((A, X))
-    opts = [autotune.tune(G, X, reps=3)[0] for G, X in zip(mats, Xs)]
+    opts, rep = autotune.tune_batch(mats, Xs, reps=3)
+    assert len(opts) == len(mats) and rep["accepted_matrices"] <= rep["changed_per_matrix"]
     B = Batched(mats, Xs, opts=opts)
     g = B.capture()
     g.replay()
