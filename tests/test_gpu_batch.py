@@ -132,3 +132,26 @@ def test_autotune_choice_is_correct_and_cached(spx, torch, tmp_path):
         f.write("{not json")
     o3, rep3 = autotune.tune(G, Xd, reps=2, cache_path=cache)  # corrupt cache: tuned again
     assert not rep3["cached"]
+
+
+def test_tune_batch_options_and_time_in_batch(spx, torch):
+    """tune_batch on a mixed batch: one option set per matrix, each a default
+    or that matrix's own pick; the batch through them is bitwise equal to the
+    single launches with the same options; time_in_batch gives a positive
+    time per copy, also for a matrix too small to fill the chip alone."""
+    from paper_1302_1078_amd import autotune
+    from paper_1302_1078_amd.batch import Batched
+    specs, mats, Xs, refs = build_set(torch, torch.float32, count=12, seed=7)
+    opts, rep = autotune.tune_batch(mats, Xs, reps=2, rounds=1)
+    assert len(opts) == len(mats)
+    assert set(rep["groups"]) <= {1, 4, 16}
+    assert 0 <= rep["accepted_matrices"] <= rep["changed_per_matrix"] <= len(mats)
+    B = Batched(mats, Xs, opts=opts)
+    Ys = B.run()
+    for i, (A, X) in enumerate(zip(mats, Xs)):
+        want = single(spx, A, X, keep_stream(spx.PlanOpts.from_dict(opts[i].to_dict())))
+        assert torch.equal(Ys[i].view(torch.int32), want.view(torch.int32)), i
+    small = min(range(len(mats)), key=lambda i: mats[i].nnz)
+    k = 1 if Xs[small].dim() == 1 else Xs[small].shape[1]
+    t = autotune.time_in_batch(mats[small], Xs[small], spx.default_opts(k, torch.float32), reps=2)
+    assert t > 0
