@@ -4,7 +4,8 @@ every output element.  The oracle's inputs are the generators' triplets
 assembled by the oracle itself; nothing it reads comes from the GPU.
 
   C1  power-law 1,048,576 rows, 16.8 M nonzeros: CSR assembly bit-exact;
-      FP64 SpMV and SpMM (k = 16).
+      FP64 SpMV (default plan and the benchmark's plan with hot x) and SpMM
+      (k = 16).
   C2  27-point stencil on 128^3 (55.7 M nonzeros) and the C1 power-law
       matrix: SpMV (k = 1) and SpMM (k = 8, 32) with FP64, FP32 and BF16
       values, every element against the oracle; the stencil's SpMM also
@@ -88,6 +89,13 @@ def test_c1_assembly_spmv_spmm(spx, torch, c1_matrix):
     x = spgen.uniform(A.n, 1)
     y = spx.spmv(G, dev(torch, x), plan=spx.Plan.for_matrix(G, spx.default_opts(1))).cpu().numpy()
     check_f64(y, A, x, "C1 SpMV")
+    # the benchmark's SpMV plan: the default bins with the 65,536 most-used
+    # columns' x entries packed (bitwise the plain plan's y)
+    import bench
+    hot = spx.Plan.for_matrix(G, spx.default_opts(1)).attach_hot_x(G, bench.HOT_X_COLUMNS)
+    yh = spx.spmv(G, dev(torch, x), plan=hot).cpu().numpy()
+    assert np.array_equal(yh.view(np.uint64), y.view(np.uint64))
+    check_f64(yh, A, x, "C1 SpMV, hot x plan")
     k = 16
     X = spgen.uniform(A.n * k, 2).reshape(A.n, k)
     Y = spx.spmm(G, dev(torch, X), plan=spx.Plan.for_matrix(G, spx.default_opts(k))).cpu().numpy()
