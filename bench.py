@@ -316,6 +316,18 @@ def bench_c2(ctx, A1=None):
                                             "max_rel_diff_vs_default_plan": float((yc.double() - yd.double()).abs().max()
                                                                                   / yd.double().abs().max())}
                     del bv, yc
+                if k == 1 and name.startswith("powerlaw"):
+                    # the same SpMV through the plan with hot x attached (the
+                    # matrix's column use is skewed; the headline step's plan)
+                    ph = spx.Plan.for_matrix(Aq, spx.default_opts(1, vals.dtype)).attach_hot_x(
+                        Aq, HOT_X_COLUMNS, xdtype=xd.dtype)
+                    yhx = torch.empty_like(yd)
+                    th = float(ctx["timer"].run([lambda: spx.spmv(Aq, xd, y=yhx, plan=ph)], ctx["fsteps"], 3)[:, 0].mean())
+                    r["hot_x_plan"] = {"us": th * 1e6, "eff_gbs": b / th / 1e9, "frac_hbm": b / th / 1e9 / PEAK_HBM_GBS,
+                                       "speedup_vs_default_plan": t / th, "hot_columns": HOT_X_COLUMNS,
+                                       "equals_default_bitwise": bool(torch.equal(yhx.view(torch.uint8),
+                                                                                  yd.view(torch.uint8)))}
+                    del ph, yhx
                 if vname != "f64":
                     r["rel2_vs_gpu_fp64"] = max(rel2(yh[:, j], y3[:, j]) for j in range(k))
                     y5 = fp64_product(A.with_values(vals.double()), Xq64, k)
