@@ -29,6 +29,8 @@ def main(argv=None):
                          "(with / without the x reads); autograd: forward + backward through the "
                          "autograd Function (values and x both require gradients); transpose_atomic: "
                          "dx = A^T dy by the atomic scatter")
+    ap.add_argument("--hot-x", type=int, default=0,
+                    help="SpMV through a plan with the x entries of this many most-used columns packed")
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--reps", type=int, default=5)
@@ -135,6 +137,10 @@ def main(argv=None):
         return
     plans = [ops.Plan.staged(A, k, xt, pipelined=args.pipelined) if args.staged
              else ops.Plan.for_matrix(A, ops.banded_opts(A, k, vt) if args.banded else ops.default_opts(k, vt))]
+    if args.hot_x:
+        if k != 1:
+            raise SystemExit("--hot-x serves the SpMV (--op spmv)")
+        plans[0].attach_hot_x(A, args.hot_x, xdtype=xt)
     for l in [int(s) for s in args.lanes.split(",") if s.strip()]:
         plans.append(ops.Plan.for_matrix(A, PlanOpts.from_dict({"nbins": 1, "upper": [], "lanes": [l],
                                                                  "split_chunk": 4096, "max_k": k})))
