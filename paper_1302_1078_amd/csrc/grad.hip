@@ -27,10 +27,10 @@ constexpr int kVisit = 4;
 // Scatter-add merging (A^T dy with k = 1): a workgroup first adds its
 // contributions into an LDS table keyed by column (linear probing, a slot
 // claimed by compare-and-swap), then adds each occupied slot to dX with one
-// atomic.  On a power-law matrix the hottest columns take one atomic per
-// workgroup instead of one per nonzero, and contention on those addresses,
-// not the number of atomics, is what bounds the plain scatter.  A
-// contribution that finds no slot within kProbes goes straight to memory.
+// atomic.  L2 forwards every global atomic to memory, so the scatter is
+// bound by how many atomics it issues; the table removes the repeats of a
+// column inside a workgroup (on a power-law matrix, the hottest columns).
+// A contribution that finds no slot within kProbes goes straight to memory.
 constexpr int kMergeSlots = 2048;
 constexpr int kMergeBits = 11;
 constexpr int kProbes = 8;
@@ -220,8 +220,11 @@ __device__ __forceinline__ void visit_stream(const ProdArgs& a, const BinDesc& d
   }
 }
 
-template <typename VT, typename XT, int MODE>
-__global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
+// One workgroup's share of a backward traversal: the bin and tile of this
+// workgroup, then its split segment, stream tile or row groups.  With MERGE
+// the scatter adds go through the workgroup's table `tb`.
+template <typename VT, typename XT, int MODE, bool MERGE>
+__device__ __forceinline__ void grad_tile(const ProdArgs& a, const MergeTab<XT>& tb) {
   const int b = blockIdx.x;
   int bi = 0;
   while (bi + 1 < a.nbins && b >= a.bins[bi + 1].blk_begin) ++bi;
@@ -237,11 +240,11 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
     const int32_t re = a.rowptr[row + 1];
     const int32_t p0 = a.rowptr[row] + (tile - f) * a.chunk;
     const int32_t p1 = min(p0 + a.chunk, re);
-    visit_run<VT, XT, MODE>(a, row, p0 + t, p1, kWG);
+    visit_run<VT, XT, MODE, MERGE>(a, row, p0 + t, p1, kWG, tb);
     return;
   }
   if (d.lanes == SPX_LANES_STREAM && a.k == 1) {
-    visit_stream<VT, XT, MODE>(a, d, tile);
+    visit_stream<VT, XT, MODE, MERGE>(a, d, tile, tb);
     return;
   }
   // row groups of G lanes; a bin may give each group several rows (rpg),
@@ -270,7 +273,12 @@ __global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
   }
 #pragma unroll
   for (int j = 0; j < kMaxRpg; ++j)
-    if (rows[j] >= 0) visit_run<VT, XT, MODE>(a, rows[j], q0[j] + t % G, q1[j], G);
+    if (rows[j] >= 0) visit_run<VT, XT, MODE, MERGE>(a, rows[j], q0[j] + t % G, q1[j], G, tb);
+}
+
+template <typename VT, typename XT, int MODE>
+__global__ __launch_bounds__(kWG) void k_grad(const ProdArgs a) {
+  grad_tile<VT, XT, MODE, false>(a, MergeTab<XT>{nullptr, nullptr});
 }
 
 // A^T dy with k = 1 through the workgroup's merge table: the same traversal as
@@ -279,54 +287,15 @@ template <typename VT, typename XT>
 __global__ __launch_bounds__(kWG) void k_scatter_merged(const ProdArgs a) {
   __shared__ int32_t s_key[kMergeSlots];
   __shared__ XT s_val[kMergeSlots];
-  const int b = blockIdx.x;
-  int bi = 0;
-  while (bi + 1 < a.nbins && b >= a.bins[bi + 1].blk_begin) ++bi;
-  const BinDesc d = a.bins[bi];
-  const int lb = b - d.blk_begin;
-  const int tile = (a.flags & SPX_FLAG_NO_XCD_MAP) ? lb : xcd_tile(lb, d.nblk);
   const int t = threadIdx.x;
   for (int i = t; i < kMergeSlots; i += kWG) {
     s_key[i] = -1;
     s_val[i] = XT(0);
   }
   __syncthreads();
-  const MergeTab<XT> tb{s_key, s_val};
-  if (d.lanes == 0) {  // one segment of a split row
-    if (tile < d.nrows) {
-      const int32_t sg = a.seg_row[tile];
-      const int32_t row = a.split_rows[sg];
-      const int32_t f = a.seg_first[sg];
-      const int32_t re = a.rowptr[row + 1];
-      const int32_t p0 = a.rowptr[row] + (tile - f) * a.chunk;
-      const int32_t p1 = min(p0 + a.chunk, re);
-      visit_run<VT, XT, kScatterT, true>(a, row, p0 + t, p1, kWG, tb);
-    }
-  } else if (d.lanes == SPX_LANES_STREAM) {
-    visit_stream<VT, XT, kScatterT, true>(a, d, tile, tb);
-  } else {
-    const int G = d.lanes;
-    const int rpg = d.rpg;
-    const int ng = kWG / G;
-    constexpr int kMaxRpg = 8;
-    int32_t rows[kMaxRpg], q0[kMaxRpg], q1[kMaxRpg];
-#pragma unroll
-    for (int j = 0; j < kMaxRpg; ++j) {
-      const int idx = (tile * rpg + j) * ng + t / G;
-      rows[j] = -1;
-      q0[j] = q1[j] = 0;
-      if (j < rpg && idx < d.nrows) rows[j] = a.row_perm ? a.row_perm[d.row_begin + idx] : d.row_begin + idx;
-    }
-#pragma unroll
-    for (int j = 0; j < kMaxRpg; ++j) {
-      if (rows[j] < 0) continue;
-      q0[j] = a.rowptr[rows[j]];
-      q1[j] = a.rowptr[rows[j] + 1];
-    }
-#pragma unroll
-    for (int j = 0; j < kMaxRpg; ++j)
-      if (rows[j] >= 0) visit_run<VT, XT, kScatterT, true>(a, rows[j], q0[j] + t % G, q1[j], G, tb);
-  }
+  // the traversal's only barriers (a stream tile's) are reached by the whole
+  // workgroup, and every thread then returns here to the barrier below
+  grad_tile<VT, XT, kScatterT, true>(a, MergeTab<XT>{s_key, s_val});
   __syncthreads();
   XT* y = static_cast<XT*>(a.Y);
   for (int i = t; i < kMergeSlots; i += kWG) {
