@@ -613,13 +613,14 @@ extern "C" spx_status bcsr_spmm(int32_t m, int32_t n, int32_t a, int32_t b, int3
     while (kl < per) kl <<= 1;
     int S = slots;
     if (S <= 0) {
-      // 16 to 32 lanes per block row measured best on the 27-point stencil
-      // (k = 8 to 32: 4 slots below 16 lanes per X row, 2 from 16 on; one
-      // slot, a wavefront per eight block rows, ran 1.5-2x slower); fewer
-      // when a block row holds less than a round of blocks per slot
+      // About 16 lanes per block row (S x KL) measured best on the 27-point
+      // stencil with FP64, FP32 and BF16 values at k = 8 to 32: 8 slots at 2
+      // lanes per X row, 4 at 4, 2 at 8 and at 16 (one slot ran 1.2-2x
+      // slower, so two at least); fewer when a block row holds less than a
+      // round of blocks per slot
       const int U = (a >= 8) ? 2 : 4;
       const double mean = static_cast<double>(nblocks) / mb;
-      S = (kl >= 16) ? 2 : 4;
+      S = (16 / kl > 2) ? 16 / kl : 2;
       if (S * kl > kWave) S = kWave / kl;
       while (S > 1 && S * U > mean) S >>= 1;
     }
