@@ -8,7 +8,9 @@ row (split segments) and a short last row, with colind[p] = p mod n and every
 value 1.  With small-integer x each y_i is an exact integer sum, checked on
 sampled rows (first, middle, the last four) against the host's sum of the
 same x entries; the rows in between are checked by their closed form where x
-is all ones."""
+is all ones.  The SpMV runs through the default plan, no plan, and the default
+plan with hot x (65,536 columns; its copy of the column indices spans the
+same int32 positions)."""
 import numpy as np
 import pytest
 
@@ -68,7 +70,8 @@ def test_spmv_at_max_nnz(big):
     sample = [0, 1, m // 2, m - 4, m - 3, m - 2, m - 1]
     want = expected(rowptr, sample, x)
     ones = torch.ones(N, dtype=torch.float32, device="cuda:0")
-    for name, plan in (("default", spx.Plan.for_matrix(A)), ("none", None)):
+    hot = spx.Plan.for_matrix(A).attach_hot_x(A, 65536, xdtype=torch.float32)   # the benchmark's SpMV plan form
+    for name, plan in (("default", spx.Plan.for_matrix(A)), ("none", None), ("hot_x", hot)):
         print(f"spmv plan={name}", flush=True)
         y = spx.spmv(A, xd, plan=plan).cpu().numpy()
         assert np.array_equal(y[sample].astype(np.float64), want), name
